@@ -1,0 +1,146 @@
+/*
+ * mpspt.h — C ABI of the MI355X (gfx950) MPS perturbation theory library.
+ *
+ * The library minimises the Hylleraas functional (Eq. hyll of Sharma & Chan,
+ * arXiv:1408.5092)
+ *     H[Psi1] = <Psi1|H0 - E0|Psi1> + 2 <Psi1|Q V|Psi0>
+ * over a first-order matrix product state |Psi1> (Eq. mps1) with the two-site
+ * sweep the paper describes, and returns the second-order energy E2 (the
+ * minimised functional, an upper bound to the exact uncontracted E2) and the
+ * third-order energy by Wigner's 2n+1 rule (Eq. 3rd).  H0 is the Dyall
+ * Hamiltonian (full H on the active orbitals plus diagonal virtual orbital
+ * energies); V = H - H0.  There are no core orbitals.
+ *
+ * Conventions
+ *  - Orbitals: active [0, k_a), then virtual [k_a, k_a + k_v).  One MPS site
+ *    per spatial orbital, local basis |0>, |up>, |dn>, |up dn> with
+ *    (N, 2Sz) = (0,0), (1,1), (1,-1), (2,0); |up dn> = a+_up a+_dn |0>, and
+ *    spin orbitals are ordered site by site, up before down.
+ *  - Bond labels are the (N, 2Sz) content of the block to the left of the
+ *    bond, one label per basis state, grouped by sector in ascending
+ *    (N, 2Sz) order.
+ *  - All host arrays are row-major double or int32, borrowed for the call
+ *    and copied; nothing is retained.  Device memory is owned by the context.
+ *  - Every call returns an mpspt_status; on failure mpspt_last_error() holds
+ *    a message.  No C++ exception crosses this boundary.  A context serves
+ *    one host thread; calls on one context must not overlap.
+ */
+#ifndef MPSPT_H
+#define MPSPT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    MPSPT_OK = 0,
+    MPSPT_E_ARG = -1,         /* bad argument: size, NaN/Inf, asymmetry, null pointer */
+    MPSPT_E_QN = -2,          /* tensor entries outside the blocks its bond labels allow */
+    MPSPT_E_NOMEM = -3,       /* device allocation failed */
+    MPSPT_E_HIP = -4,         /* HIP runtime error (message has the HIP error string) */
+    MPSPT_E_INDEFINITE = -5,  /* CG met p.Ap <= 0: H0 - E0 not positive definite locally */
+    MPSPT_E_STATE = -6,       /* call out of order (e.g. sweep before Psi0 is loaded) */
+    MPSPT_E_NODEV = -7        /* no usable gfx950 device */
+} mpspt_status;
+
+typedef struct mpspt_ctx mpspt_ctx;
+
+/* Create a context on HIP device `hip_device`, issuing all work on
+ * `hip_stream` (a borrowed hipStream_t; NULL = the null stream).
+ * Fails with MPSPT_E_NODEV when the device does not exist. */
+mpspt_status mpspt_create(int hip_device, void *hip_stream, mpspt_ctx **out);
+/* Free the context and all device memory it owns.  NULL-safe. */
+void mpspt_destroy(mpspt_ctx *ctx);
+/* Last error message of the context (owned by it), or a static string. */
+const char *mpspt_last_error(const mpspt_ctx *ctx);
+
+/* Hamiltonian H = sum_pq h_pq E_pq + 1/2 sum_pqrs (pq|rs)(E_pq E_rs - d_qr E_ps)
+ * (the paper's H; the one- and two-electron parts of the model).
+ * h: k*k symmetric (k = k_a + k_v).  B: n_chol*k*k Cholesky vectors, each
+ * symmetric, with (pq|rs) = sum_L B[L][p][q] B[L][r][s].
+ * Errors: MPSPT_E_ARG on k_a < 1, k_v < 1, k > 128, asymmetry or non-finite values. */
+mpspt_status mpspt_load_integrals(mpspt_ctx *ctx, int32_t k_a, int32_t k_v, const double *h,
+                                  int32_t n_chol, const double *B);
+/* Same with explicit chemists' integrals eri[p][q][r][s] = (pq|rs), k^4 values,
+ * 8-fold symmetric (for special cases with no Cholesky form). */
+mpspt_status mpspt_load_integrals_eri(mpspt_ctx *ctx, int32_t k_a, int32_t k_v, const double *h,
+                                      const double *eri);
+/* Zeroth-order partition (the paper uses Dyall's H0, kind = 0): eps_virt[k_v]
+ * are the diagonal virtual energies in H0; V = H - H0 keeps the rest. */
+mpspt_status mpspt_load_h0_partition(mpspt_ctx *ctx, int32_t kind, const double *eps_virt);
+
+/* Reference state Psi0 on the k_a active sites, any gauge, need not be
+ * normalised.  bond_dims[k_a+1] with bond_dims[0] = bond_dims[k_a] = 1;
+ * bond_qn: 2 ints (N, 2Sz) per basis state, bond after bond;
+ * site[i]: dense [D_i][4][D_{i+1}].  The library extends Psi0 by empty
+ * virtual sites, normalises it and computes E0 = <Psi0|H0|Psi0>.
+ * Errors: MPSPT_E_QN if any entry lies outside an allowed block or the last
+ * label is not (n_elec, two_sz). */
+mpspt_status mpspt_load_psi0(mpspt_ctx *ctx, int32_t n_elec, int32_t two_sz, const int32_t *bond_dims,
+                             const int32_t *bond_qn, const double *const *site);
+/* Starting first-order MPS on all k_a + k_v sites (same layout), restricted to
+ * one or two electrons in virtual orbitals.  Required before mpspt_sweep. */
+mpspt_status mpspt_load_psi1_guess(mpspt_ctx *ctx, const int32_t *bond_dims, const int32_t *bond_qn,
+                                   const double *const *site);
+
+typedef struct {
+    int32_t M1;           /* bond dimension of Psi1 */
+    int32_t n_sweeps;     /* > 0: run exactly this many sweeps; 0: until |dE2| < e_tol */
+    int32_t max_sweeps;   /* cap when n_sweeps == 0 (<= 64) */
+    double e_tol;         /* sweep-to-sweep E2 change that ends the run */
+    double cg_rel_tol;    /* local solve stops when |A x + b| <= cg_rel_tol |b| */
+    int32_t cg_max_iter;  /* cap on CG iterations per local solve */
+    int32_t compute_e3;   /* 1: evaluate E3 on the final state */
+} mpspt_sweep_params;
+
+typedef struct {
+    double e0;              /* <Psi0|H0|Psi0> */
+    double e2;              /* Hylleraas value of the final two-site state */
+    double e3;              /* <Psi1|V|Psi1> - E1 <Psi1|Psi1> (E1 = 0 without core orbitals) */
+    int32_t n_sweeps_done;
+    int32_t n_steps;        /* local solves performed */
+    double e2_sweep[64];    /* E2 at the end of each sweep */
+    double max_discarded;   /* largest discarded weight of the last sweep */
+    int64_t cg_iters;       /* total CG iterations */
+    int64_t sigma_calls;    /* applications of H0_eff - E0 */
+    double sigma_flops;     /* algorithmic flops of those applications */
+    double sigma_bytes;     /* algorithmic bytes (environments, vectors) of those applications */
+    double t_total_s;       /* wall time of the sweeps (host clock, device synchronised) */
+    int32_t flags;          /* bit 0: some local CG hit cg_max_iter (value still an upper bound) */
+} mpspt_result;
+
+/* Run the sweep.  Errors: MPSPT_E_STATE if integrals, partition, Psi0 or the
+ * Psi1 guess are missing; MPSPT_E_INDEFINITE if CG meets p.Ap <= 0. */
+mpspt_status mpspt_sweep(mpspt_ctx *ctx, const mpspt_sweep_params *params, mpspt_result *out);
+
+/* Per local solve of the last mpspt_sweep: running E2, CG iterations,
+ * discarded weight, seconds since the sweep started.  Up to cap entries;
+ * *n_out = number available.  Null output pointers are skipped. */
+mpspt_status mpspt_get_trace(const mpspt_ctx *ctx, int32_t cap, double *e2, int32_t *cg_iters,
+                             double *discarded, double *t_s, int32_t *n_out);
+/* Sector table of a bond of Psi1 (which = 0) or of the extended Psi0
+ * (which = 1): triples (N, 2Sz, dim) in ascending order, up to cap triples. */
+mpspt_status mpspt_get_bond(const mpspt_ctx *ctx, int32_t which, int32_t bond, int32_t cap,
+                            int32_t *qn_dims, int32_t *n_out);
+/* Dense copy [D_l][4][D_r] of a site tensor of the current Psi1 (which = 0)
+ * or extended Psi0 (which = 1).  dims[2] receives (D_l, D_r). */
+mpspt_status mpspt_get_site(mpspt_ctx *ctx, int32_t which, int32_t site, size_t cap, double *dense,
+                            int32_t *dims);
+
+/* Host-only validation hook: contract one of the library's MPOs
+ * (which = 0: H0, 1: the part of V acting on Psi0, 2: V) to a dense
+ * 4^n x 4^n matrix, n = k_a + k_v <= 6, site 0 most significant.
+ * eri as in mpspt_load_integrals_eri.  Needs no device. */
+mpspt_status mpspt_mpo_dense(int32_t k_a, int32_t k_v, const double *h, const double *eri,
+                             const double *eps_virt, int32_t which, double *out, size_t cap);
+/* Channel counts per bond (n+1 values) of the same MPO. */
+mpspt_status mpspt_mpo_dims(int32_t k_a, int32_t k_v, const double *h, const double *eri,
+                            const double *eps_virt, int32_t which, int32_t *dims, int32_t cap);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MPSPT_H */

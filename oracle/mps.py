@@ -284,7 +284,7 @@ class Sweeper:
             self.A[i] = C
             self._upd_right(i + 1)
 
-    def run(self, n_sweeps=None, e_tol=1e-9, max_sweeps=10):
+    def run(self, n_sweeps=None, e_tol=1e-9, max_sweeps=10, on_step=None):
         n = self.n
         self.right_canonicalize()
         x0 = np.einsum('asb,btc->astc', self.A[0], self.A[1])
@@ -314,6 +314,8 @@ class Sweeper:
                                            cg_iters=it, converged=conv, discarded=disc,
                                            bond=bond))
                     self.x_last = x
+                    if on_step is not None:
+                        on_step(self.trace[-1])
             e_sweep.append(self.trace[-1]["e2"])
             sweep += 1
             if n_sweeps is not None:

@@ -1,0 +1,111 @@
+// Device-side primitives of the MPS-PT engine (implemented in kernels.hip).
+//
+// The host engine expresses every contraction as a work list of small dense
+// block operations and hands it to one of these grouped kernels.  Work lists
+// are output-stationary: each group owns one output block and sums all of
+// its terms in a fixed order, so results are deterministic and no atomics
+// are involved.
+#pragma once
+#include <cstddef>
+#include <cstdint>
+#include <string>
+
+namespace mpspt {
+namespace dev {
+
+// C (m x n, leading dimension ldc) [+]= sum_t alpha_t op(A_t) op(B_t)
+struct GemmTerm {
+    const double* A;
+    const double* B;
+    double alpha;
+    int32_t lda, ldb, k;
+    int32_t transA, transB;  // op(A) = A^T when set (A stored k x m)
+};
+struct GemmGroup {
+    double* C;
+    int32_t ldc, m, n;
+    int32_t term0, nterms;
+    int32_t accumulate;  // 0: overwrite C, 1: add to C
+    int32_t tile0;       // first tile index of this group in the launch
+};
+
+// dst (m x n) [+]= sum_t alpha_t op(src_t)
+struct AxpyTerm {
+    const double* src;
+    int32_t lds, trans;
+    double alpha;
+};
+struct AxpyGroup {
+    double* dst;
+    int32_t ldd, m, n;
+    int32_t term0, nterms;
+    int32_t accumulate;
+    int32_t pad;
+};
+
+// dst (m x n) = shift + sum_t c_t L_t[i * ls] R_t[j * rs]
+struct DiagTerm {
+    const double* L;
+    const double* R;
+    int32_t ls, rs;
+    double c;
+};
+struct DiagGroup {
+    double* dst;
+    int32_t ldd, m, n;
+    int32_t term0, nterms;
+    double shift;
+};
+
+// Symmetric eigenproblem: A (n x n, row major) is replaced by its
+// eigenvectors (columns, eigenvalues descending), w receives eigenvalues;
+// V is n x n workspace.
+struct EigJob {
+    double* A;
+    double* V;
+    double* w;
+    int32_t n, pad;
+};
+
+struct Error {
+    int code;  // mpspt_status value
+    std::string msg;
+};
+
+void set_device(int device, void* stream);  // throws Error
+int device_count();
+void* alloc(size_t bytes);                  // throws Error (MPSPT_E_NOMEM)
+void release(void* p);
+void h2d(void* dst, const void* src, size_t bytes);
+void d2h(void* dst, const void* src, size_t bytes);  // synchronous
+void d2d(void* dst, const void* src, size_t bytes);
+void zero(void* p, size_t bytes);
+void sync();
+double now();  // host seconds
+
+void gemm_grouped(const GemmGroup* groups, int ngroups, const GemmTerm* terms, int ntiles);
+void axpy_grouped(const AxpyGroup* groups, int ngroups, const AxpyTerm* terms);
+void diag_grouped(const DiagGroup* groups, int ngroups, const DiagTerm* terms);
+void eig_batched(const EigJob* jobs, int njobs);
+
+// Vector kernels over length-n double vectors.  `scal` is a small device
+// array of scalars (layout in kernels.hip); all reductions are fixed-order.
+enum Scalar { S_PQ = 0, S_RZ0 = 1, S_RZ1 = 2, S_RR = 3, S_BB = 4, S_DOT = 5, S_N = 8 };
+void dot(const double* a, const double* b, size_t n, double* scal, int slot, double* partials);
+// r = -b - q ; z = r / d ; p = z ; scal[RZ0] = r.z ; scal[RR] = r.r ; scal[BB] = b.b
+void cg_init(double* r, double* z, double* p, const double* b, const double* q, const double* d,
+             size_t n, double* scal, double* partials);
+// q -= shift * p ; scal[PQ] = p.q
+void cg_shift_dot(double* q, const double* p, double shift, size_t n, double* scal, double* partials);
+// alpha = rz_cur / pq ; x += alpha p ; r -= alpha q ; z = r / d ; scal[rz_new] = r.z ; scal[RR] = r.r
+void cg_update(double* x, double* r, double* z, const double* p, const double* q, const double* d,
+               size_t n, double* scal, int rz_cur, int rz_new, double* partials);
+// p = z + (rz_new / rz_cur) p
+void cg_direction(double* p, const double* z, size_t n, const double* scal, int rz_cur, int rz_new);
+// y = a x + b y
+void axpby(double* y, const double* x, double a, double b, size_t n);
+
+constexpr int kPartials = 512;  // size of the partials workspace (doubles)
+
+}  // namespace dev
+}  // namespace mpspt

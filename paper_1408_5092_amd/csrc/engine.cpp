@@ -1,0 +1,1071 @@
+// Two-site MPS-PT sweep (host driver).
+//
+// Window (i, i+1) of Psi1 is optimised with the rest fixed: the partial
+// derivative of the Hylleraas functional with respect to the two-site tensor
+// x vanishes when (H0_eff - E0) x = -b with b = <local basis|V|Psi0>; this is
+// solved by Jacobi-preconditioned CG, its functional value x.(A x) + 2 x.b is
+// the running E2, and x is split by the reduced density matrix of the half
+// being renormalised, keeping the M1 most significant states.  Environments
+// of <Psi1|H0|Psi1> and of the mixed <Psi1|V|Psi0> are carried along.
+#include "engine.hpp"
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <stdexcept>
+#include <unordered_map>
+
+#include "../../include/mpspt.h"
+
+namespace mpspt {
+
+namespace {
+dev::Error err(int code, const std::string& m) { return dev::Error{code, m}; }
+constexpr int kTile = 32;
+}  // namespace
+
+// ------------------------------------------------------------- storage
+void DevBuf::reset() {
+    if (p) {
+        dev::sync();
+        dev::release(p);
+    }
+    p = nullptr;
+    n = 0;
+}
+void DevBuf::alloc(size_t c) {
+    reset();
+    if (c) p = static_cast<double*>(dev::alloc(c * sizeof(double)));
+    n = c;
+}
+void DevBuf::ensure(size_t c) {
+    if (c > n) alloc(c + c / 4 + 64);
+}
+
+int Bond::find(QN x) const {
+    auto it = std::lower_bound(q.begin(), q.end(), x);
+    if (it == q.end() || *it != x) return -1;
+    return (int)(it - q.begin());
+}
+int Bond::total() const {
+    int t = 0;
+    for (int v : d) t += v;
+    return t;
+}
+
+Site make_site(const Bond& L, const Bond& R) {
+    Site s;
+    s.L = L;
+    s.R = R;
+    const int nl = (int)L.q.size();
+    s.idx.assign((size_t)nl * 4, -1);
+    s.pw.assign(nl, 0);
+    s.po.assign(nl, 0);
+    s.by_jr.assign(R.q.size(), {});
+    size_t off = 0;
+    for (int il = 0; il < nl; ++il) {
+        s.po[il] = off;
+        int col = 0;
+        for (int st = 0; st < 4; ++st) {
+            int jr = R.find(L.q[il] + site_dq(st));
+            if (jr < 0) continue;
+            s.idx[il * 4 + st] = (int)s.blk.size();
+            s.by_jr[jr].push_back((int)s.blk.size());
+            s.blk.push_back({il, st, jr, L.d[il], R.d[jr], col});
+            col += R.d[jr];
+        }
+        s.pw[il] = col;
+        off += (size_t)L.d[il] * col;
+    }
+    s.size = off;
+    s.data.alloc(off);
+    return s;
+}
+
+Two make_two(const Bond& L, const Bond& R, const std::set<QN>* mid_ok) {
+    Two t;
+    t.L = L;
+    t.R = R;
+    const int nl = (int)L.q.size();
+    t.idx.assign((size_t)nl * 16, -1);
+    t.pw.assign(nl, 0);
+    t.po.assign(nl, 0);
+    size_t off = 0;
+    for (int il = 0; il < nl; ++il) {
+        t.po[il] = off;
+        int col = 0;
+        for (int s1 = 0; s1 < 4; ++s1) {
+            QN mid = L.q[il] + site_dq(s1);
+            if (mid_ok && !mid_ok->count(mid)) continue;
+            for (int s2 = 0; s2 < 4; ++s2) {
+                int jr = R.find(mid + site_dq(s2));
+                if (jr < 0) continue;
+                t.idx[(il * 4 + s1) * 4 + s2] = (int)t.blk.size();
+                t.blk.push_back({il, s1, s2, jr, L.d[il], R.d[jr], col});
+                col += R.d[jr];
+            }
+        }
+        t.pw[il] = col;
+        off += (size_t)L.d[il] * col;
+    }
+    t.size = off;
+    return t;
+}
+
+void Env::index() {
+    idx.assign((size_t)nch * bra.q.size(), -1);
+    by_w.assign(nch, {});
+    for (size_t b = 0; b < blk.size(); ++b) {
+        idx[(size_t)blk[b].w * bra.q.size() + blk[b].ib] = (int)b;
+        by_w[blk[b].w].push_back((int)b);
+    }
+}
+
+TwoOp make_twoop(const MPO& m, int i) {
+    TwoOp O;
+    O.nin = m.dims[i];
+    O.nout = m.dims[i + 2];
+    const auto& W1 = m.W[i];
+    const auto& W2 = m.W[i + 1];
+    std::vector<std::vector<int>> in_mid(m.dims[i + 1]), out_mid(m.dims[i + 1]);
+    for (size_t e = 0; e < W1.size(); ++e) in_mid[W1[e].cout].push_back((int)e);
+    for (size_t e = 0; e < W2.size(); ++e) out_mid[W2[e].cin].push_back((int)e);
+    std::map<std::tuple<int, int, int, int>, double> acc;  // (w'*16+s1'*4+s2', w, s1, s2)
+    for (int mid = 0; mid < m.dims[i + 1]; ++mid)
+        for (int a : in_mid[mid])
+            for (int b : out_mid[mid]) {
+                const MPOEntry& e1 = W1[a];
+                const MPOEntry& e2 = W2[b];
+                for (int s1p = 0; s1p < 4; ++s1p)
+                    for (int s1 = 0; s1 < 4; ++s1) {
+                        double v1 = e1.m[s1p * 4 + s1];
+                        if (v1 == 0.0) continue;
+                        for (int s2p = 0; s2p < 4; ++s2p)
+                            for (int s2 = 0; s2 < 4; ++s2) {
+                                double v2 = e2.m[s2p * 4 + s2];
+                                if (v2 == 0.0) continue;
+                                acc[{e2.cout * 16 + s1p * 4 + s2p, e1.cin, s1, s2}] += v1 * v2;
+                            }
+                    }
+            }
+    O.by_out.assign((size_t)O.nout * 16, {});
+    for (auto& kv : acc) {
+        if (kv.second == 0.0) continue;
+        O.by_out[std::get<0>(kv.first)].push_back(
+            {std::get<1>(kv.first), std::get<2>(kv.first), std::get<3>(kv.first), kv.second});
+    }
+    return O;
+}
+
+// ---------------------------------------------------------- work lists
+void GemmBatch::group(double* C, int ldc, int m, int n, bool acc) {
+    if (m <= 0 || n <= 0) {
+        g_.push_back({nullptr, 0, 0, 0, (int)t_.size(), 0, 1, -1});  // placeholder, dropped
+        return;
+    }
+    dev::GemmGroup g{C, ldc, m, n, (int)t_.size(), 0, acc ? 1 : 0, tiles_};
+    tiles_ += ((m + kTile - 1) / kTile) * ((n + kTile - 1) / kTile);
+    g_.push_back(g);
+}
+void GemmBatch::term(const double* A, int lda, bool tA, const double* B, int ldb, bool tB, int k, double alpha) {
+    dev::GemmGroup& g = g_.back();
+    if (g.tile0 < 0 || k <= 0 || alpha == 0.0) return;
+    t_.push_back({A, B, alpha, lda, ldb, k, tA ? 1 : 0, tB ? 1 : 0});
+    ++g.nterms;
+    flops_ += 2.0 * g.m * g.n * k;
+}
+void GemmBatch::upload() {
+    std::vector<dev::GemmGroup> keep;
+    keep.reserve(g_.size());
+    for (auto& g : g_)
+        if (g.tile0 >= 0) keep.push_back(g);
+    g_.swap(keep);
+    dg_.upload(g_);
+    dt_.upload(t_);
+}
+void GemmBatch::run() const {
+    if (tiles_ > 0) dev::gemm_grouped(dg_.p, (int)g_.size(), dt_.p, tiles_);
+}
+
+void AxpyBatch::group(double* dst, int ldd, int m, int n, bool acc) {
+    g_.push_back({dst, ldd, m, n, (int)t_.size(), 0, acc ? 1 : 0, 0});
+}
+void AxpyBatch::term(const double* src, int lds, bool trans, double alpha) {
+    dev::AxpyGroup& g = g_.back();
+    t_.push_back({src, lds, trans ? 1 : 0, alpha});
+    ++g.nterms;
+    flops_ += 2.0 * g.m * g.n;
+}
+void AxpyBatch::upload() {
+    std::vector<dev::AxpyGroup> keep;
+    for (auto& g : g_)
+        if (g.m > 0 && g.n > 0) keep.push_back(g);
+    g_.swap(keep);
+    dg_.upload(g_);
+    dt_.upload(t_);
+}
+void AxpyBatch::run() const {
+    if (!g_.empty()) dev::axpy_grouped(dg_.p, (int)g_.size(), dt_.p);
+}
+
+// ------------------------------------------------------------- inputs
+void Engine::set_integrals(int k_a, int k_v, std::vector<double> h, std::vector<double> eri) {
+    k_a_ = k_a;
+    k_v_ = k_v;
+    n_ = k_a + k_v;
+    h_ = std::move(h);
+    eri_ = std::move(eri);
+    have_ints = true;
+    have_part = have_psi0 = have_psi1 = false;
+}
+
+void Engine::set_partition(std::vector<double> eps) {
+    if (!have_ints) throw err(MPSPT_E_STATE, "load integrals before the H0 partition");
+    eps_ = std::move(eps);
+    build_mpos();
+    have_part = true;
+    have_psi0 = have_psi1 = false;
+}
+
+void Engine::build_mpos() {
+    mpo_h0_ = build_mpo(OpKind::H0, k_a_, k_v_, h_, eri_, eps_);
+    mpo_v_ = build_mpo(OpKind::VPsi0, k_a_, k_v_, h_, eri_, eps_);
+}
+
+void Engine::load_site(Site& s, const std::vector<double>& dense) {
+    const int Dl = s.L.total(), Dr = s.R.total();
+    if (dense.size() != (size_t)Dl * 4 * Dr) throw err(MPSPT_E_ARG, "site tensor size does not match bond dimensions");
+    std::vector<int> ol(s.L.q.size() + 1, 0), orr(s.R.q.size() + 1, 0);
+    for (size_t a = 0; a < s.L.q.size(); ++a) ol[a + 1] = ol[a] + s.L.d[a];
+    for (size_t a = 0; a < s.R.q.size(); ++a) orr[a + 1] = orr[a] + s.R.d[a];
+    std::vector<char> covered(dense.size(), 0);
+    std::vector<double> host(s.size, 0.0);
+    for (size_t b = 0; b < s.blk.size(); ++b) {
+        const auto& B = s.blk[b];
+        size_t base = s.po[B.il] + B.col;
+        for (int r = 0; r < B.rows; ++r)
+            for (int c = 0; c < B.cols; ++c) {
+                size_t di = ((size_t)(ol[B.il] + r) * 4 + B.s) * Dr + orr[B.jr] + c;
+                host[base + (size_t)r * s.pw[B.il] + c] = dense[di];
+                covered[di] = 1;
+            }
+    }
+    for (size_t i = 0; i < dense.size(); ++i) {
+        if (!std::isfinite(dense[i])) throw err(MPSPT_E_ARG, "non-finite entry in a site tensor");
+        if (!covered[i] && dense[i] != 0.0) throw err(MPSPT_E_QN, "site tensor entry outside the blocks its labels allow");
+    }
+    if (s.size) dev::h2d(s.data.p, host.data(), s.size * sizeof(double));
+}
+
+Env Engine::trivial_env(const Bond& bra, const Bond& ket) const {
+    Env e;
+    e.nch = 1;
+    e.bra = bra;
+    e.ket = ket;
+    e.blk.push_back({0, 0, 0, 1, 1, 0});
+    e.size = 1;
+    e.dq = {QN{0, 0}};
+    e.index();
+    e.data.alloc(1);
+    double one = 1.0;
+    dev::h2d(e.data.p, &one, sizeof(double));
+    return e;
+}
+
+static MPO identity_mpo(int n) {
+    MPO m;
+    m.n = n;
+    m.dims.assign(n + 1, 1);
+    m.dq.assign(n + 1, std::vector<QN>{QN{0, 0}});
+    m.W.resize(n);
+    for (int i = 0; i < n; ++i) {
+        MPOEntry e{0, 0, {0}};
+        for (int s = 0; s < 4; ++s) e.m[s * 4 + s] = 1.0;
+        m.W[i].push_back(e);
+    }
+    return m;
+}
+
+void Engine::set_psi0(int n_elec, int two_sz, const std::vector<Bond>& bonds,
+                      const std::vector<std::vector<double>>& sites) {
+    if (!have_part) throw err(MPSPT_E_STATE, "load integrals and the H0 partition before Psi0");
+    if ((int)bonds.size() != k_a_ + 1 || (int)sites.size() != k_a_) throw err(MPSPT_E_ARG, "Psi0 needs k_a sites");
+    if (bonds[0].q.size() != 1 || bonds[0].q[0] != QN{0, 0} || bonds[0].d[0] != 1)
+        throw err(MPSPT_E_QN, "first bond of Psi0 must be the single label (0, 0)");
+    if (bonds[k_a_].q.size() != 1 || bonds[k_a_].q[0] != QN{n_elec, two_sz} || bonds[k_a_].d[0] != 1)
+        throw err(MPSPT_E_QN, "last bond of Psi0 must be the single label (n_elec, two_sz)");
+    N_ = n_elec;
+    tsz_ = two_sz;
+    std::vector<Bond> b = bonds;
+    for (int i = k_a_ + 1; i <= n_; ++i) b.push_back(bonds[k_a_]);
+    P0_.clear();
+    for (int i = 0; i < n_; ++i) {
+        P0_.push_back(make_site(b[i], b[i + 1]));
+        if (i < k_a_) {
+            load_site(P0_[i], sites[i]);
+        } else {
+            std::vector<double> v(4, 0.0);
+            v[0] = 1.0;
+            load_site(P0_[i], v);
+        }
+    }
+    // normalise and E0 = <Psi0|H0|Psi0>
+    MPO idm = identity_mpo(n_);
+    Env ov = trivial_env(b[0], b[0]), eh = trivial_env(b[0], b[0]);
+    for (int i = 0; i < n_; ++i) {
+        Env o2, e2;
+        env_left(o2, ov, P0_[i], P0_[i], idm, i);
+        env_left(e2, eh, P0_[i], P0_[i], mpo_h0_, i);
+        ov = std::move(o2);
+        eh = std::move(e2);
+    }
+    double norm = 0, eh0 = 0;
+    if (ov.blk.size() != 1 || eh.blk.size() != 1) throw err(MPSPT_E_QN, "Psi0 has no weight in its target sector");
+    dev::d2h(&norm, ov.data.p, sizeof(double));
+    dev::d2h(&eh0, eh.data.p, sizeof(double));
+    if (!(norm > 0.0)) throw err(MPSPT_E_ARG, "Psi0 has zero norm");
+    E0_ = eh0 / norm;
+    dev::axpby(P0_[0].data.p, P0_[0].data.p, 0.0, 1.0 / std::sqrt(norm), P0_[0].size);
+    P0x_lay_.clear();
+    P0x_.clear();
+    for (int i = 0; i + 1 < n_; ++i) {
+        P0x_lay_.push_back(make_two(b[i], b[i + 2], nullptr));
+        P0x_.emplace_back();
+        P0x_.back().alloc(std::max<size_t>(P0x_lay_.back().size, 1));
+        contract_sites(P0_[i], P0_[i + 1], P0x_lay_.back(), P0x_.back().p);
+    }
+    // admissible (N, 2Sz) at every bond of Psi1: one or two virtual electrons
+    std::vector<std::set<std::tuple<int, int, int>>> left(n_ + 1), right(n_ + 1);
+    left[0].insert({0, 0, 0});
+    for (int i = 0; i < n_; ++i)
+        for (auto& t : left[i])
+            for (int s = 0; s < 4; ++s) {
+                QN d = site_dq(s);
+                left[i + 1].insert({std::get<0>(t) + d.n, std::get<1>(t) + d.s, std::get<2>(t) + (i >= k_a_ ? d.n : 0)});
+            }
+    right[n_].insert({0, 0, 0});
+    for (int i = n_ - 1; i >= 0; --i)
+        for (auto& t : right[i + 1])
+            for (int s = 0; s < 4; ++s) {
+                QN d = site_dq(s);
+                right[i].insert({std::get<0>(t) + d.n, std::get<1>(t) + d.s, std::get<2>(t) + (i >= k_a_ ? d.n : 0)});
+            }
+    adm_.assign(n_ + 1, {});
+    for (int bb = 0; bb <= n_; ++bb)
+        for (auto& l : left[bb])
+            for (int nvr = 0; nvr <= 2; ++nvr) {
+                int nv = std::get<2>(l) + nvr;
+                if (nv < 1 || nv > 2) continue;
+                if (right[bb].count({N_ - std::get<0>(l), tsz_ - std::get<1>(l), nvr}))
+                    adm_[bb].insert(QN{std::get<0>(l), std::get<1>(l)});
+            }
+    have_psi0 = true;
+    have_psi1 = false;
+}
+
+void Engine::set_psi1(const std::vector<Bond>& bonds, const std::vector<std::vector<double>>& sites) {
+    if (!have_psi0) throw err(MPSPT_E_STATE, "load Psi0 before the Psi1 guess");
+    if ((int)bonds.size() != n_ + 1 || (int)sites.size() != n_) throw err(MPSPT_E_ARG, "Psi1 needs k_a + k_v sites");
+    if (bonds[0].q.size() != 1 || bonds[0].q[0] != QN{0, 0} || bonds[0].d[0] != 1)
+        throw err(MPSPT_E_QN, "first bond of Psi1 must be the single label (0, 0)");
+    if (bonds[n_].q.size() != 1 || bonds[n_].q[0] != QN{N_, tsz_} || bonds[n_].d[0] != 1)
+        throw err(MPSPT_E_QN, "last bond of Psi1 must be the single label (n_elec, two_sz)");
+    for (int b = 0; b <= n_; ++b)
+        for (auto& q : bonds[b].q)
+            if (!adm_[b].count(q)) throw err(MPSPT_E_QN, "Psi1 bond sector outside the one/two virtual electron space");
+    // validate now (block structure), keep host copies for each sweep call
+    for (int i = 0; i < n_; ++i) {
+        Site s = make_site(bonds[i], bonds[i + 1]);
+        load_site(s, sites[i]);
+    }
+    psi1_bonds_ = bonds;
+    psi1_guess_ = sites;
+    have_psi1 = true;
+}
+
+// ------------------------------------------------------ contractions
+void Engine::contract_sites(const Site& A, const Site& B, const Two& lay, double* out) {
+    GemmBatch g;
+    for (size_t b = 0; b < lay.blk.size(); ++b) {
+        const auto& X = lay.blk[b];
+        g.group(out + lay.off((int)b), lay.ld((int)b), X.rows, X.cols, false);
+        int a = A.idx[X.il * 4 + X.s1];
+        if (a < 0) continue;
+        int jm = A.blk[a].jr;
+        int bb = B.idx[jm * 4 + X.s2];
+        if (bb < 0 || B.blk[bb].jr != X.jr) continue;
+        g.term(A.at(a), A.ld(a), false, B.at(bb), B.ld(bb), false, A.blk[a].cols, 1.0);
+    }
+    g.upload();
+    g.run();
+}
+
+void Engine::env_left(Env& out, const Env& L, const Site& Abra, const Site& Aket, const MPO& m, int i) {
+    out = Env();
+    out.nch = m.dims[i + 1];
+    out.bra = Abra.R;
+    out.ket = Aket.R;
+    // stage a: T[lb] = L block . row panel of Aket
+    std::vector<size_t> toff(L.blk.size(), (size_t)-1);
+    size_t tsz = 0;
+    for (size_t lb = 0; lb < L.blk.size(); ++lb) {
+        int ik = L.blk[lb].ik;
+        if (Aket.pw[ik] == 0) continue;
+        toff[lb] = tsz;
+        tsz += (size_t)L.blk[lb].rows * Aket.pw[ik];
+    }
+    T_.ensure(std::max<size_t>(tsz, 1));
+    GemmBatch ga;
+    for (size_t lb = 0; lb < L.blk.size(); ++lb) {
+        if (toff[lb] == (size_t)-1) continue;
+        const auto& B = L.blk[lb];
+        ga.group(T_.p + toff[lb], Aket.pw[B.ik], B.rows, Aket.pw[B.ik], false);
+        ga.term(L.data.p + B.off, B.cols, false, Aket.data.p + Aket.po[B.ik], Aket.pw[B.ik], false, B.cols, 1.0);
+    }
+    // stage b: contributions per output block (channel, bra sector)
+    struct Tm { const double* A; int lda; const double* B; int ldb; int k; double a; };
+    std::map<std::pair<int, int>, std::pair<int, std::vector<Tm>>> outs;
+    for (const MPOEntry& e : m.W[i]) {
+        for (int s = 0; s < 4; ++s)
+            for (int t = 0; t < 4; ++t) {
+                double v = e.m[s * 4 + t];
+                if (v == 0.0) continue;
+                for (int lb : L.by_w[e.cin]) {
+                    if (toff[lb] == (size_t)-1) continue;
+                    const auto& B = L.blk[lb];
+                    int ab = Abra.idx[B.ib * 4 + s];
+                    int ak = Aket.idx[B.ik * 4 + t];
+                    if (ab < 0 || ak < 0) continue;
+                    int ibp = Abra.blk[ab].jr, ikp = Aket.blk[ak].jr;
+                    auto& o = outs[{e.cout, ibp}];
+                    if (o.second.empty()) o.first = ikp;
+                    else if (o.first != ikp) throw err(MPSPT_E_QN, "inconsistent channel quantum numbers");
+                    o.second.push_back({Abra.at(ab), Abra.ld(ab), T_.p + toff[lb] + Aket.blk[ak].col,
+                                        Aket.pw[B.ik], B.rows, v});
+                }
+            }
+    }
+    size_t off = 0;
+    for (auto& kv : outs) {
+        int w = kv.first.first, ib = kv.first.second, ik = kv.second.first;
+        out.blk.push_back({w, ib, ik, out.bra.d[ib], out.ket.d[ik], off});
+        off += (size_t)out.bra.d[ib] * out.ket.d[ik];
+    }
+    out.size = off;
+    out.dq = m.dq[i + 1];
+    out.index();
+    out.data.alloc(std::max<size_t>(off, 1));
+    GemmBatch gb;
+    size_t bi = 0;
+    for (auto& kv : outs) {
+        const auto& B = out.blk[bi++];
+        gb.group(out.data.p + B.off, B.cols, B.rows, B.cols, false);
+        for (const Tm& t : kv.second.second) gb.term(t.A, t.lda, true, t.B, t.ldb, false, t.k, t.a);
+    }
+    ga.upload();
+    gb.upload();
+    ga.run();
+    gb.run();
+}
+
+void Engine::env_right(Env& out, const Env& R, const Site& Abra, const Site& Aket, const MPO& m, int i) {
+    out = Env();
+    out.nch = m.dims[i];
+    out.bra = Abra.L;
+    out.ket = Aket.L;
+    struct Tm { const double* A; int lda; size_t toff; int ldb; int k; double a; };
+    std::unordered_map<uint64_t, size_t> tmap;  // (R block, Aket block) -> offset in T
+    struct Ta { int rb, ak; size_t off; };
+    std::vector<Ta> tlist;
+    size_t tsz = 0;
+    std::map<std::pair<int, int>, std::pair<int, std::vector<Tm>>> outs;
+    for (const MPOEntry& e : m.W[i]) {
+        for (int s = 0; s < 4; ++s)
+            for (int t = 0; t < 4; ++t) {
+                double v = e.m[s * 4 + t];
+                if (v == 0.0) continue;
+                for (int rb : R.by_w[e.cout]) {
+                    const auto& B = R.blk[rb];
+                    for (int ab : Abra.by_jr[B.ib]) {
+                        if (Abra.blk[ab].s != s) continue;
+                        for (int ak : Aket.by_jr[B.ik]) {
+                            if (Aket.blk[ak].s != t) continue;
+                            uint64_t key = (uint64_t)rb << 32 | (uint32_t)ak;
+                            auto it = tmap.find(key);
+                            size_t to;
+                            if (it == tmap.end()) {
+                                to = tsz;
+                                tmap.emplace(key, to);
+                                tlist.push_back({rb, ak, to});
+                                tsz += (size_t)B.rows * Aket.blk[ak].rows;
+                            } else {
+                                to = it->second;
+                            }
+                            int ibp = Abra.blk[ab].il, ikp = Aket.blk[ak].il;
+                            auto& o = outs[{e.cin, ibp}];
+                            if (o.second.empty()) o.first = ikp;
+                            else if (o.first != ikp) throw err(MPSPT_E_QN, "inconsistent channel quantum numbers");
+                            o.second.push_back({Abra.at(ab), Abra.ld(ab), to, Aket.blk[ak].rows, B.rows, v});
+                        }
+                    }
+                }
+            }
+    }
+    T_.ensure(std::max<size_t>(tsz, 1));
+    GemmBatch ga;
+    for (const Ta& t : tlist) {
+        const auto& B = R.blk[t.rb];
+        const auto& K = Aket.blk[t.ak];
+        ga.group(T_.p + t.off, K.rows, B.rows, K.rows, false);
+        ga.term(R.data.p + B.off, B.cols, false, Aket.at(t.ak), Aket.ld(t.ak), true, B.cols, 1.0);
+    }
+    size_t off = 0;
+    for (auto& kv : outs) {
+        int w = kv.first.first, ib = kv.first.second, ik = kv.second.first;
+        out.blk.push_back({w, ib, ik, out.bra.d[ib], out.ket.d[ik], off});
+        off += (size_t)out.bra.d[ib] * out.ket.d[ik];
+    }
+    out.size = off;
+    out.dq = m.dq[i];
+    out.index();
+    out.data.alloc(std::max<size_t>(off, 1));
+    GemmBatch gb;
+    size_t bi = 0;
+    for (auto& kv : outs) {
+        const auto& B = out.blk[bi++];
+        gb.group(out.data.p + B.off, B.cols, B.rows, B.cols, false);
+        for (const Tm& t : kv.second.second) gb.term(t.A, t.lda, false, T_.p + t.toff, t.ldb, false, t.k, t.a);
+    }
+    ga.upload();
+    gb.upload();
+    ga.run();
+    gb.run();
+}
+
+void Engine::build_effop(EffOp& op, const Env& L, const Env& R, const TwoOp& O, const Two& ket,
+                         const double* xket, const Two& bra, double* ybra) {
+    op.st1.clear();
+    op.st2.clear();
+    op.st3.clear();
+    op.flops = op.bytes = 0;
+    // stage 1 layout: U[lb] = L block . ket row panel
+    std::vector<size_t> uoff(L.blk.size(), (size_t)-1);
+    size_t usz = 0;
+    std::vector<char> lused(L.blk.size(), 0), rused(R.blk.size(), 0);
+    for (size_t lb = 0; lb < L.blk.size(); ++lb) {
+        int ik = L.blk[lb].ik;
+        if (ket.pw[ik] == 0) continue;
+        uoff[lb] = usz;
+        usz += (size_t)L.blk[lb].rows * ket.pw[ik];
+    }
+    // stage 2 layout: V blocks per (bra block, w')
+    struct VT { size_t usrc; int lds; double a; };
+    struct VB { int bb, rb; size_t off; int rows, cols; std::vector<VT> t; };
+    std::vector<VB> vbs;
+    size_t vsz = 0;
+    for (size_t bb = 0; bb < bra.blk.size(); ++bb) {
+        const auto& Y = bra.blk[bb];
+        for (int wp = 0; wp < R.nch; ++wp) {
+            int rb = R.find(wp, Y.jr);
+            if (rb < 0) continue;
+            const auto& terms = O.by_out[(size_t)wp * 16 + Y.s1 * 4 + Y.s2];
+            if (terms.empty()) continue;
+            int jrk = R.blk[rb].ik;
+            VB v{(int)bb, rb, 0, Y.rows, R.blk[rb].cols, {}};
+            for (const auto& t : terms) {
+                QN qk = bra.L.q[Y.il] - L.dq[t.w];
+                int ik = ket.L.find(qk);
+                if (ik < 0) continue;
+                int lb = L.find(t.w, Y.il);
+                if (lb < 0 || L.blk[lb].ik != ik || uoff[lb] == (size_t)-1) continue;
+                int xb = ket.idx[(ik * 4 + t.s1) * 4 + t.s2];
+                if (xb < 0 || ket.blk[xb].jr != jrk) continue;
+                v.t.push_back({uoff[lb] + ket.blk[xb].col, ket.pw[ik], t.v});
+                lused[lb] = 1;
+            }
+            if (v.t.empty()) continue;
+            v.off = vsz;
+            vsz += (size_t)v.rows * v.cols;
+            rused[rb] = 1;
+            vbs.push_back(std::move(v));
+        }
+    }
+    op.U.ensure(std::max<size_t>(usz, 1));
+    op.V.ensure(std::max<size_t>(vsz, 1));
+    for (size_t lb = 0; lb < L.blk.size(); ++lb) {
+        if (uoff[lb] == (size_t)-1 || !lused[lb]) continue;
+        const auto& B = L.blk[lb];
+        op.st1.group(op.U.p + uoff[lb], ket.pw[B.ik], B.rows, ket.pw[B.ik], false);
+        op.st1.term(L.data.p + B.off, B.cols, false, xket + ket.po[B.ik], ket.pw[B.ik], false, B.cols, 1.0);
+        op.bytes += 8.0 * B.rows * B.cols;
+    }
+    for (const VB& v : vbs) {
+        op.st2.group(op.V.p + v.off, v.cols, v.rows, v.cols, false);
+        for (const VT& t : v.t) op.st2.term(op.U.p + t.usrc, t.lds, false, t.a);
+    }
+    size_t vi = 0;
+    for (size_t bb = 0; bb < bra.blk.size(); ++bb) {
+        const auto& Y = bra.blk[bb];
+        op.st3.group(ybra + bra.off((int)bb), bra.ld((int)bb), Y.rows, Y.cols, false);
+        while (vi < vbs.size() && vbs[vi].bb == (int)bb) {
+            const VB& v = vbs[vi++];
+            const auto& RB = R.blk[v.rb];
+            op.st3.term(op.V.p + v.off, v.cols, false, R.data.p + RB.off, RB.cols, true, v.cols, 1.0);
+        }
+    }
+    for (size_t rb = 0; rb < R.blk.size(); ++rb)
+        if (rused[rb]) op.bytes += 8.0 * R.blk[rb].rows * R.blk[rb].cols;
+    op.bytes += 8.0 * (ket.size + bra.size);
+    op.st1.upload();
+    op.st2.upload();
+    op.st3.upload();
+    op.flops = op.st1.flops() + op.st2.flops() + op.st3.flops();
+}
+
+void Engine::build_diag(const Env& L, const Env& R, const TwoOp& O, const Two& lay, double* d, double shift) {
+    std::vector<dev::DiagGroup> gs;
+    std::vector<dev::DiagTerm> ts;
+    for (size_t bb = 0; bb < lay.blk.size(); ++bb) {
+        const auto& Y = lay.blk[bb];
+        dev::DiagGroup g{d + lay.off((int)bb), lay.ld((int)bb), Y.rows, Y.cols, (int)ts.size(), 0, shift};
+        for (int wp = 0; wp < R.nch; ++wp) {
+            int rb = R.find(wp, Y.jr);
+            if (rb < 0 || R.blk[rb].ik != Y.jr) continue;
+            for (const auto& t : O.by_out[(size_t)wp * 16 + Y.s1 * 4 + Y.s2]) {
+                if (t.s1 != Y.s1 || t.s2 != Y.s2) continue;
+                int lb = L.find(t.w, Y.il);
+                if (lb < 0 || L.blk[lb].ik != Y.il) continue;
+                ts.push_back({L.data.p + L.blk[lb].off, R.data.p + R.blk[rb].off, L.blk[lb].cols + 1,
+                              R.blk[rb].cols + 1, t.v});
+                ++g.nterms;
+            }
+        }
+        if (Y.rows > 0 && Y.cols > 0) gs.push_back(g);
+    }
+    DevArr<dev::DiagGroup> dg;
+    DevArr<dev::DiagTerm> dt;
+    dg.upload(gs);
+    dt.upload(ts);
+    if (!gs.empty()) dev::diag_grouped(dg.p, (int)gs.size(), dt.p);
+    dev::sync();
+}
+
+// ----------------------------------------------------------- truncation
+namespace {
+struct Sel {
+    std::vector<int> kept;  // per group
+    double disc = 0;
+};
+// Keep the M largest eigenvalues over all sectors (ties by sector, then
+// index); drop eigenvalues <= 1e-14 of the trace; never cut between two
+// eigenvalues within a relative 1e-4 of each other (spin multiplets stay
+// whole) unless that would keep nothing.
+Sel select_states(const std::vector<std::vector<double>>& w, int M) {
+    struct E { double l; int g, j; };
+    std::vector<E> all;
+    double tr = 0;
+    for (size_t g = 0; g < w.size(); ++g)
+        for (size_t j = 0; j < w[g].size(); ++j) {
+            all.push_back({w[g][j], (int)g, (int)j});
+            tr += w[g][j];
+        }
+    std::stable_sort(all.begin(), all.end(), [](const E& a, const E& b) {
+        if (a.l != b.l) return a.l > b.l;
+        if (a.g != b.g) return a.g < b.g;
+        return a.j < b.j;
+    });
+    int nsig = 0;
+    if (tr > 0)
+        for (auto& e : all) nsig += e.l > 1e-14 * tr;
+    int K0 = std::min(M, nsig), K = K0;
+    while (K > 0 && K < (int)all.size() && all[K - 1].l <= (1.0 + 1e-4) * all[K].l) --K;
+    if (K == 0) K = K0;
+    Sel s;
+    s.kept.assign(w.size(), 0);
+    double kept = 0;
+    for (int i = 0; i < K; ++i) {
+        s.kept[all[i].g]++;
+        kept += all[i].l;
+    }
+    s.disc = tr > 0 ? 1.0 - kept / tr : 0.0;
+    return s;
+}
+}  // namespace
+
+double Engine::truncate(int i, bool forward, const Two& lay, const double* x, int M, Site& C) {
+    // groups of rows (forward: (il, s1)) or columns (backward: (s2, jr)) by middle sector
+    struct Part { int a, b, off, dim; };  // forward: a=il b=s1 ; backward: a=s2 b=jr
+    std::map<QN, std::vector<Part>> groups;
+    if (forward) {
+        for (int il = 0; il < (int)lay.L.q.size(); ++il)
+            for (int s1 = 0; s1 < 4; ++s1) {
+                bool any = false;
+                for (int s2 = 0; s2 < 4; ++s2) any |= lay.idx[(il * 4 + s1) * 4 + s2] >= 0;
+                if (any) groups[lay.L.q[il] + site_dq(s1)].push_back({il, s1, 0, lay.L.d[il]});
+            }
+    } else {
+        std::set<std::pair<int, int>> cols;
+        for (const auto& Y : lay.blk) cols.insert({Y.s2, Y.jr});
+        for (auto& c : cols) groups[lay.R.q[c.second] - site_dq(c.first)].push_back({c.first, c.second, 0, lay.R.d[c.second]});
+    }
+    std::vector<QN> gq;
+    std::vector<int> gdim;
+    std::vector<size_t> goff;
+    size_t rsz = 0;
+    for (auto& kv : groups) {
+        int d = 0;
+        for (auto& p : kv.second) { p.off = d; d += p.dim; }
+        gq.push_back(kv.first);
+        gdim.push_back(d);
+        goff.push_back(rsz);
+        rsz += (size_t)d * d;
+    }
+    const int ng = (int)gq.size();
+    for (int d : gdim)
+        if (d > 512) throw err(MPSPT_E_ARG, "density-matrix sector larger than 512 (eigensolver limit)");
+    rho_.ensure(std::max<size_t>(rsz, 1));
+    eigV_.ensure(std::max<size_t>(rsz, 1));
+    size_t wsz = 0;
+    std::vector<size_t> woff(ng);
+    for (int g = 0; g < ng; ++g) { woff[g] = wsz; wsz += gdim[g]; }
+    eigw_.ensure(std::max<size_t>(wsz, 1));
+    // reduced density matrices
+    GemmBatch gr;
+    int g = 0;
+    for (auto& kv : groups) {
+        const auto& parts = kv.second;
+        const int d = gdim[g];
+        for (const auto& pa : parts)
+            for (const auto& pb : parts) {
+                gr.group(rho_.p + goff[g] + (size_t)pa.off * d + pb.off, d, pa.dim, pb.dim, false);
+                if (forward) {
+                    for (int s2 = 0; s2 < 4; ++s2) {
+                        int xa = lay.idx[(pa.a * 4 + pa.b) * 4 + s2];
+                        int xb = lay.idx[(pb.a * 4 + pb.b) * 4 + s2];
+                        if (xa < 0 || xb < 0) continue;
+                        gr.term(x + lay.off(xa), lay.ld(xa), false, x + lay.off(xb), lay.ld(xb), true,
+                                lay.blk[xa].cols, 1.0);
+                    }
+                } else {
+                    for (int il = 0; il < (int)lay.L.q.size(); ++il)
+                        for (int s1 = 0; s1 < 4; ++s1) {
+                            int xa = lay.idx[(il * 4 + s1) * 4 + pa.a];
+                            int xb = lay.idx[(il * 4 + s1) * 4 + pb.a];
+                            if (xa < 0 || xb < 0 || lay.blk[xa].jr != pa.b || lay.blk[xb].jr != pb.b) continue;
+                            gr.term(x + lay.off(xa), lay.ld(xa), true, x + lay.off(xb), lay.ld(xb), false,
+                                    lay.L.d[il], 1.0);
+                        }
+                }
+            }
+        ++g;
+    }
+    gr.upload();
+    gr.run();
+    std::vector<dev::EigJob> jobs;
+    for (int q = 0; q < ng; ++q)
+        if (gdim[q] > 0) jobs.push_back({rho_.p + goff[q], eigV_.p + goff[q], eigw_.p + woff[q], gdim[q], 0});
+    DevArr<dev::EigJob> dj;
+    dj.upload(jobs);
+    if (!jobs.empty()) dev::eig_batched(dj.p, (int)jobs.size());
+    std::vector<double> wall(std::max<size_t>(wsz, 1));
+    dev::d2h(wall.data(), eigw_.p, wsz * sizeof(double));
+    std::vector<std::vector<double>> w(ng);
+    for (int q = 0; q < ng; ++q) w[q].assign(wall.begin() + woff[q], wall.begin() + woff[q] + gdim[q]);
+    Sel sel = select_states(w, M);
+    Bond nb;
+    std::vector<int> gid;  // new sector -> group
+    for (int q = 0; q < ng; ++q)
+        if (sel.kept[q] > 0) {
+            nb.q.push_back(gq[q]);
+            nb.d.push_back(sel.kept[q]);
+            gid.push_back(q);
+        }
+    if (nb.q.empty()) throw err(MPSPT_E_STATE, "truncation kept no states (zero two-site tensor)");
+    std::vector<std::vector<Part>*> gparts;
+    for (auto& kv : groups) gparts.push_back(&kv.second);
+    const double* EV = rho_.p;  // eigenvectors replace the density matrices
+    if (forward) {
+        Site An = make_site(lay.L, nb);
+        AxpyBatch cp;
+        for (size_t b = 0; b < An.blk.size(); ++b) {
+            const auto& B = An.blk[b];
+            int q = gid[B.jr];
+            cp.group(An.at((int)b), An.ld((int)b), B.rows, B.cols, false);
+            for (const auto& p : *gparts[q])
+                if (p.a == B.il && p.b == B.s) cp.term(EV + goff[q] + (size_t)p.off * gdim[q], gdim[q], false, 1.0);
+        }
+        C = make_site(nb, lay.R);
+        GemmBatch gc;
+        for (size_t b = 0; b < C.blk.size(); ++b) {
+            const auto& B = C.blk[b];
+            int q = gid[B.il];
+            gc.group(C.at((int)b), C.ld((int)b), B.rows, B.cols, false);
+            for (const auto& p : *gparts[q]) {
+                int xb = lay.idx[(p.a * 4 + p.b) * 4 + B.s];
+                if (xb < 0) continue;
+                gc.term(EV + goff[q] + (size_t)p.off * gdim[q], gdim[q], true, x + lay.off(xb), lay.ld(xb), false,
+                        p.dim, 1.0);
+            }
+        }
+        cp.upload();
+        gc.upload();
+        // zero blocks with no terms are written by the kernels (overwrite mode)
+        cp.run();
+        gc.run();
+        A_[i] = std::move(An);
+    } else {
+        Site An = make_site(nb, lay.R);
+        AxpyBatch cp;
+        for (size_t b = 0; b < An.blk.size(); ++b) {
+            const auto& B = An.blk[b];
+            int q = gid[B.il];
+            cp.group(An.at((int)b), An.ld((int)b), B.rows, B.cols, false);
+            for (const auto& p : *gparts[q])
+                if (p.a == B.s && p.b == B.jr) cp.term(EV + goff[q] + (size_t)p.off * gdim[q], gdim[q], true, 1.0);
+        }
+        C = make_site(lay.L, nb);
+        GemmBatch gc;
+        for (size_t b = 0; b < C.blk.size(); ++b) {
+            const auto& B = C.blk[b];
+            int q = gid[B.jr];
+            gc.group(C.at((int)b), C.ld((int)b), B.rows, B.cols, false);
+            for (const auto& p : *gparts[q]) {
+                int xb = lay.idx[(B.il * 4 + B.s) * 4 + p.a];
+                if (xb < 0 || lay.blk[xb].jr != p.b) continue;
+                gc.term(x + lay.off(xb), lay.ld(xb), false, EV + goff[q] + (size_t)p.off * gdim[q], gdim[q], false,
+                        p.dim, 1.0);
+            }
+        }
+        cp.upload();
+        gc.upload();
+        cp.run();
+        gc.run();
+        A_[i + 1] = std::move(An);
+    }
+    return sel.disc;
+}
+
+void Engine::upd_left(int i) {
+    env_left(LH_[i + 1], LH_[i], A_[i], A_[i], mpo_h0_, i);
+    env_left(LV_[i + 1], LV_[i], A_[i], P0_[i], mpo_v_, i);
+}
+
+void Engine::upd_right(int i) {
+    env_right(RH_[i], RH_[i + 1], A_[i], A_[i], mpo_h0_, i);
+    env_right(RV_[i], RV_[i + 1], A_[i], P0_[i], mpo_v_, i);
+}
+
+// ---------------------------------------------------------- local solve
+int Engine::solve(int i, double& e2) {
+    const Two& lay = xlay_;
+    const size_t n = lay.size;
+    for (DevBuf* b : {&x_, &b_, &d_, &r_, &z_, &p_, &q_}) b->ensure(std::max<size_t>(n, 1));
+    partials_.ensure(dev::kPartials);
+    scal_.ensure(dev::S_N);
+    TwoOp O = make_twoop(mpo_h0_, i);
+    TwoOp Ov = make_twoop(mpo_v_, i);
+    EffOp rhs;
+    build_effop(rhs, LV_[i], RV_[i + 2], Ov, P0x_lay_[i], P0x_[i].p, lay, b_.p);
+    rhs.run();
+    build_diag(LH_[i], RH_[i + 2], O, lay, d_.p, -E0_);
+    EffOp sig;
+    build_effop(sig, LH_[i], RH_[i + 2], O, lay, p_.p, lay, q_.p);
+    auto apply = [&]() {
+        sig.run();
+        dev::cg_shift_dot(q_.p, p_.p, E0_, n, scal_.p, partials_.p);
+        res_.sigma_calls++;
+        res_.flops += sig.flops;
+        res_.bytes += sig.bytes;
+    };
+    double sc[dev::S_N];
+    dev::d2d(x_.p, xg_.p, n * sizeof(double));
+    dev::d2d(p_.p, x_.p, n * sizeof(double));
+    apply();
+    dev::cg_init(r_.p, z_.p, p_.p, b_.p, q_.p, d_.p, n, scal_.p, partials_.p);
+    dev::d2h(sc, scal_.p, sizeof(sc));
+    const double bb = sc[dev::S_BB];
+    int it = 0;
+    if (bb == 0.0) {
+        dev::zero(x_.p, n * sizeof(double));
+    } else {
+        int cur = dev::S_RZ0, nxt = dev::S_RZ1;
+        double rr = sc[dev::S_RR];
+        while (rr > cg_tol2_ * bb) {
+            if (it >= cg_max_) {
+                res_.flags |= 1;
+                break;
+            }
+            apply();
+            dev::cg_update(x_.p, r_.p, z_.p, p_.p, q_.p, d_.p, n, scal_.p, cur, nxt, partials_.p);
+            dev::d2h(sc, scal_.p, sizeof(sc));
+            ++it;
+            if (!(sc[dev::S_PQ] > 0.0))
+                throw err(MPSPT_E_INDEFINITE, "CG met p.Ap <= 0: H0 - E0 is not positive definite on the local space");
+            rr = sc[dev::S_RR];
+            if (rr <= cg_tol2_ * bb) break;
+            dev::cg_direction(p_.p, z_.p, n, scal_.p, cur, nxt);
+            std::swap(cur, nxt);
+        }
+    }
+    // Hylleraas value of x: x.(A x) + 2 x.b
+    dev::d2d(p_.p, x_.p, n * sizeof(double));
+    apply();
+    dev::dot(x_.p, b_.p, n, scal_.p, dev::S_DOT, partials_.p);
+    dev::d2h(sc, scal_.p, sizeof(sc));
+    e2 = sc[dev::S_PQ] + 2.0 * sc[dev::S_DOT];
+    return it;
+}
+
+void Engine::next_guess(int i, bool forward, Site& C) {
+    Two lay;
+    if (forward) {
+        if (i < n_ - 2) {
+            lay = make_two(C.L, A_[i + 2].R, &adm_[i + 2]);
+            xg_.ensure(std::max<size_t>(lay.size, 1));
+            contract_sites(C, A_[i + 2], lay, xg_.p);
+        } else {
+            lay = make_two(A_[i].L, C.R, &adm_[i + 1]);
+            xg_.ensure(std::max<size_t>(lay.size, 1));
+            contract_sites(A_[i], C, lay, xg_.p);
+            A_[i + 1] = std::move(C);
+        }
+    } else {
+        if (i > 0) {
+            lay = make_two(A_[i - 1].L, C.R, &adm_[i]);
+            xg_.ensure(std::max<size_t>(lay.size, 1));
+            contract_sites(A_[i - 1], C, lay, xg_.p);
+        } else {
+            lay = make_two(C.L, A_[1].R, &adm_[1]);
+            xg_.ensure(std::max<size_t>(lay.size, 1));
+            contract_sites(C, A_[1], lay, xg_.p);
+            A_[0] = std::move(C);
+        }
+    }
+    xlay_ = std::move(lay);
+}
+
+double Engine::e3_final(int window) {
+    MPO mf = build_mpo(OpKind::VFull, k_a_, k_v_, h_, eri_, eps_);
+    Env R = trivial_env(A_[n_ - 1].R, A_[n_ - 1].R);
+    for (int j = n_ - 1; j >= window + 2; --j) {
+        Env R2;
+        env_right(R2, R, A_[j], A_[j], mf, j);
+        R = std::move(R2);
+    }
+    Env L = trivial_env(A_[0].L, A_[0].L);
+    if (window != 0) throw err(MPSPT_E_STATE, "E3 is evaluated at the first window");
+    TwoOp O = make_twoop(mf, window);
+    EffOp op;
+    build_effop(op, L, R, O, last_lay_, x_.p, last_lay_, q_.p);
+    op.run();
+    dev::dot(x_.p, q_.p, last_lay_.size, scal_.p, dev::S_DOT, partials_.p);
+    double sc[dev::S_N];
+    dev::d2h(sc, scal_.p, sizeof(sc));
+    return sc[dev::S_DOT];
+}
+
+SweepResult Engine::sweep(const SweepParams& p) {
+    if (!have_psi1) throw err(MPSPT_E_STATE, "load integrals, the H0 partition, Psi0 and a Psi1 guess first");
+    if (p.M1 < 1) throw err(MPSPT_E_ARG, "M1 must be positive");
+    res_ = SweepResult();
+    res_.e0 = E0_;
+    trace_.clear();
+    cg_tol2_ = p.cg_rel_tol * p.cg_rel_tol;
+    cg_max_ = p.cg_max_iter;
+    dev::sync();
+    t0_ = dev::now();
+    A_.clear();
+    for (int i = 0; i < n_; ++i) {
+        A_.push_back(make_site(psi1_bonds_[i], psi1_bonds_[i + 1]));
+        load_site(A_[i], psi1_guess_[i]);
+    }
+    for (auto* v : {&LH_, &RH_, &LV_, &RV_}) {
+        v->clear();
+        v->resize(n_ + 1);
+    }
+    LH_[0] = trivial_env(A_[0].L, A_[0].L);
+    LV_[0] = trivial_env(A_[0].L, P0_[0].L);
+    RH_[n_] = trivial_env(A_[n_ - 1].R, A_[n_ - 1].R);
+    RV_[n_] = trivial_env(A_[n_ - 1].R, P0_[n_ - 1].R);
+    // right-canonical start: backward pass without solves
+    for (int i = n_ - 2; i >= 0; --i) {
+        Two lay = make_two(A_[i].L, A_[i + 1].R, &adm_[i + 1]);
+        x_.ensure(std::max<size_t>(lay.size, 1));
+        contract_sites(A_[i], A_[i + 1], lay, x_.p);
+        Site C;
+        truncate(i, false, lay, x_.p, p.M1, C);
+        A_[i] = std::move(C);
+        upd_right(i + 1);
+    }
+    xlay_ = make_two(A_[0].L, A_[1].R, &adm_[1]);
+    xg_.ensure(std::max<size_t>(xlay_.size, 1));
+    contract_sites(A_[0], A_[1], xlay_, xg_.p);
+    double e2 = 0;
+    for (int sw = 0; sw < 64; ++sw) {
+        double maxd = 0;
+        for (int dir = 0; dir < 2; ++dir) {
+            const bool fwd = dir == 0;
+            for (int k = 0; k < n_ - 1; ++k) {
+                const int i = fwd ? k : n_ - 2 - k;
+                int it = solve(i, e2);
+                res_.cg_iters += it;
+                last_lay_ = xlay_;
+                Site C;
+                double disc = truncate(i, fwd, xlay_, x_.p, p.M1, C);
+                if (fwd) upd_left(i);
+                else upd_right(i + 1);
+                next_guess(i, fwd, C);
+                dev::sync();
+                trace_.push_back({e2, disc, dev::now() - t0_, it});
+                maxd = std::max(maxd, disc);
+                res_.n_steps++;
+            }
+        }
+        res_.e2_sweep.push_back(e2);
+        res_.n_sweeps = sw + 1;
+        res_.max_disc = maxd;
+        if (p.n_sweeps > 0) {
+            if (res_.n_sweeps >= p.n_sweeps) break;
+        } else {
+            size_t ns = res_.e2_sweep.size();
+            if (ns > 1 && std::fabs(res_.e2_sweep[ns - 1] - res_.e2_sweep[ns - 2]) < p.e_tol) break;
+            if (res_.n_sweeps >= p.max_sweeps) break;
+        }
+    }
+    res_.e2 = e2;
+    dev::sync();
+    res_.t_total = dev::now() - t0_;
+    if (p.compute_e3) res_.e3 = e3_final(0);
+    return res_;
+}
+
+const Bond& Engine::bond(int which, int b) const {
+    if (b < 0 || b > n_) throw err(MPSPT_E_ARG, "bond index out of range");
+    if (which == 0) {
+        if (A_.empty()) throw err(MPSPT_E_STATE, "no Psi1 yet");
+        return b < n_ ? A_[b].L : A_[n_ - 1].R;
+    }
+    if (P0_.empty()) throw err(MPSPT_E_STATE, "no Psi0 yet");
+    return b < n_ ? P0_[b].L : P0_[n_ - 1].R;
+}
+
+void Engine::site_dense(int which, int i, std::vector<double>& out, int& Dl, int& Dr) const {
+    const std::vector<Site>& v = which == 0 ? A_ : P0_;
+    if (i < 0 || i >= (int)v.size()) throw err(MPSPT_E_ARG, "site index out of range");
+    const Site& s = v[i];
+    Dl = s.L.total();
+    Dr = s.R.total();
+    std::vector<double> host(s.size);
+    if (s.size) dev::d2h(host.data(), s.data.p, s.size * sizeof(double));
+    out.assign((size_t)Dl * 4 * Dr, 0.0);
+    std::vector<int> ol(s.L.q.size() + 1, 0), orr(s.R.q.size() + 1, 0);
+    for (size_t a = 0; a < s.L.q.size(); ++a) ol[a + 1] = ol[a] + s.L.d[a];
+    for (size_t a = 0; a < s.R.q.size(); ++a) orr[a + 1] = orr[a] + s.R.d[a];
+    for (const auto& B : s.blk)
+        for (int r = 0; r < B.rows; ++r)
+            for (int c = 0; c < B.cols; ++c)
+                out[((size_t)(ol[B.il] + r) * 4 + B.s) * Dr + orr[B.jr] + c] =
+                    host[s.po[B.il] + B.col + (size_t)r * s.pw[B.il] + c];
+}
+
+}  // namespace mpspt

@@ -1,0 +1,249 @@
+// Host side of the MPS-PT sweep: block-sparse tensors, work-list builders and
+// the two-site sweep driver.  All arithmetic on tensor data runs in the
+// grouped device kernels of device.hpp.
+#pragma once
+#include <map>
+#include <memory>
+#include <set>
+#include <string>
+#include <vector>
+
+#include "device.hpp"
+#include "mpo.hpp"
+
+namespace mpspt {
+
+// ---------------------------------------------------------------- storage
+class DevBuf {
+  public:
+    DevBuf() = default;
+    DevBuf(const DevBuf&) = delete;
+    DevBuf& operator=(const DevBuf&) = delete;
+    DevBuf(DevBuf&& o) noexcept { swap(o); }
+    DevBuf& operator=(DevBuf&& o) noexcept { swap(o); return *this; }
+    ~DevBuf() { reset(); }
+    void reset();
+    void alloc(size_t count);   // exactly count doubles; contents undefined
+    void ensure(size_t count);  // at least count doubles; contents undefined when it grows
+    double* p = nullptr;
+    size_t n = 0;
+
+  private:
+    void swap(DevBuf& o) { std::swap(p, o.p); std::swap(n, o.n); }
+};
+
+template <class T>
+class DevArr {
+  public:
+    DevArr() = default;
+    DevArr(const DevArr&) = delete;
+    DevArr& operator=(const DevArr&) = delete;
+    ~DevArr() {
+        if (p) {
+            dev::sync();
+            dev::release(p);
+        }
+    }
+    void upload(const std::vector<T>& v) {
+        if (v.size() > cap) {
+            if (p) dev::release(p);
+            cap = v.size() + v.size() / 2 + 16;
+            p = static_cast<T*>(dev::alloc(cap * sizeof(T)));
+        }
+        if (!v.empty()) dev::h2d(p, v.data(), v.size() * sizeof(T));
+    }
+    T* p = nullptr;
+    size_t cap = 0;
+};
+
+struct Bond {
+    std::vector<QN> q;
+    std::vector<int> d;
+    int find(QN x) const;
+    int total() const;
+    bool operator==(const Bond& o) const { return q == o.q && d == o.d; }
+};
+
+// MPS site tensor: blocks (left sector il, local state s) -> right sector jr,
+// stored as one row panel per left sector with its blocks side by side.
+struct Site {
+    Bond L, R;
+    struct Blk { int il, s, jr, rows, cols, col; };
+    std::vector<Blk> blk;
+    std::vector<int> idx;      // il * 4 + s -> block or -1
+    std::vector<int> pw;       // panel width per left sector
+    std::vector<size_t> po;    // panel offset per left sector
+    std::vector<std::vector<int>> by_jr;
+    size_t size = 0;
+    DevBuf data;
+    double* at(int b) const { return data.p + po[blk[b].il] + blk[b].col; }
+    int ld(int b) const { return pw[blk[b].il]; }
+};
+Site make_site(const Bond& L, const Bond& R);
+
+// Two-site tensor of a window: blocks (il, s1, s2) -> jr, one row panel per il.
+struct Two {
+    Bond L, R;
+    struct Blk { int il, s1, s2, jr, rows, cols, col; };
+    std::vector<Blk> blk;
+    std::vector<int> idx;      // (il * 4 + s1) * 4 + s2 -> block or -1
+    std::vector<int> pw;
+    std::vector<size_t> po;
+    size_t size = 0;
+    size_t off(int b) const { return po[blk[b].il] + blk[b].col; }
+    int ld(int b) const { return pw[blk[b].il]; }
+};
+Two make_two(const Bond& L, const Bond& R, const std::set<QN>* mid_ok);
+
+// Environment: per MPO channel w a block-sparse bra x ket matrix whose
+// blocks (ib, ik) satisfy q_bra = q_ket + dq(w).
+struct Env {
+    int nch = 0;
+    Bond bra, ket;
+    struct Blk { int w, ib, ik, rows, cols; size_t off; };
+    std::vector<Blk> blk;
+    std::vector<int> idx;      // w * nbra + ib -> block or -1
+    std::vector<std::vector<int>> by_w;
+    std::vector<QN> dq;        // per channel
+    size_t size = 0;
+    DevBuf data;
+    int find(int w, int ib) const { return idx[(size_t)w * bra.q.size() + ib]; }
+    void index();
+};
+
+// Two-site operator of a window: sum over the middle channel of W_i (x) W_{i+1}.
+struct TwoOp {
+    struct E { int w, s1, s2; double v; };
+    int nin = 0, nout = 0;
+    std::vector<std::vector<E>> by_out;  // (w' * 16 + s1' * 4 + s2') -> terms
+};
+TwoOp make_twoop(const MPO& m, int i);
+
+// Work list of grouped GEMMs, reusable across launches.
+class GemmBatch {
+  public:
+    void clear() { g_.clear(); t_.clear(); tiles_ = 0; flops_ = 0; }
+    void group(double* C, int ldc, int m, int n, bool acc);
+    void term(const double* A, int lda, bool tA, const double* B, int ldb, bool tB, int k, double alpha);
+    void upload();
+    void run() const;
+    bool empty() const { return g_.empty(); }
+    double flops() const { return flops_; }
+    size_t nterms() const { return t_.size(); }
+
+  private:
+    std::vector<dev::GemmGroup> g_;
+    std::vector<dev::GemmTerm> t_;
+    DevArr<dev::GemmGroup> dg_;
+    DevArr<dev::GemmTerm> dt_;
+    int tiles_ = 0;
+    double flops_ = 0;
+};
+
+class AxpyBatch {
+  public:
+    void clear() { g_.clear(); t_.clear(); flops_ = 0; }
+    void group(double* dst, int ldd, int m, int n, bool acc);
+    void term(const double* src, int lds, bool trans, double alpha);
+    void upload();
+    void run() const;
+    bool empty() const { return g_.empty(); }
+    double flops() const { return flops_; }
+
+  private:
+    std::vector<dev::AxpyGroup> g_;
+    std::vector<dev::AxpyTerm> t_;
+    DevArr<dev::AxpyGroup> dg_;
+    DevArr<dev::AxpyTerm> dt_;
+    double flops_ = 0;
+};
+
+// y = sum L (x) O (x) R applied to x (three grouped launches).
+struct EffOp {
+    GemmBatch st1;
+    AxpyBatch st2;
+    GemmBatch st3;
+    DevBuf U, V;
+    double flops = 0, bytes = 0;
+    void run() const { st1.run(); st2.run(); st3.run(); }
+};
+
+struct StepRecord {
+    double e2, discarded, t;
+    int cg_iters;
+};
+
+struct SweepParams {
+    int M1 = 16, n_sweeps = 0, max_sweeps = 10, cg_max_iter = 500, compute_e3 = 1;
+    double e_tol = 1e-9, cg_rel_tol = 1e-10;
+};
+
+struct SweepResult {
+    double e0 = 0, e2 = 0, e3 = 0, max_disc = 0, flops = 0, bytes = 0, t_total = 0;
+    int n_sweeps = 0, n_steps = 0, flags = 0;
+    long long cg_iters = 0, sigma_calls = 0;
+    std::vector<double> e2_sweep;
+};
+
+class Engine {
+  public:
+    // inputs
+    void set_integrals(int k_a, int k_v, std::vector<double> h, std::vector<double> eri);
+    void set_partition(std::vector<double> eps);
+    void set_psi0(int n_elec, int two_sz, const std::vector<Bond>& bonds, const std::vector<std::vector<double>>& sites);
+    void set_psi1(const std::vector<Bond>& bonds, const std::vector<std::vector<double>>& sites);
+    SweepResult sweep(const SweepParams& p);
+
+    const std::vector<StepRecord>& trace() const { return trace_; }
+    const Bond& bond(int which, int b) const;
+    int n_sites() const { return n_; }
+    int k_a() const { return k_a_; }
+    int k_v() const { return k_v_; }
+    void site_dense(int which, int i, std::vector<double>& out, int& Dl, int& Dr) const;
+
+    bool have_ints = false, have_part = false, have_psi0 = false, have_psi1 = false;
+
+  private:
+    // problem
+    int k_a_ = 0, k_v_ = 0, n_ = 0, N_ = 0, tsz_ = 0;
+    std::vector<double> h_, eri_, eps_;
+    MPO mpo_h0_, mpo_v_;
+    double E0_ = 0;
+    // states
+    std::vector<Site> P0_;      // extended Psi0
+    std::vector<Two> P0x_lay_;  // two-site layouts of Psi0 per window
+    std::vector<DevBuf> P0x_;
+    std::vector<Site> A_;       // Psi1
+    std::vector<std::set<QN>> adm_;
+    // environments
+    std::vector<Env> LH_, RH_, LV_, RV_;
+    // work buffers
+    DevBuf T_, rho_, eigV_, eigw_, partials_, scal_;
+    DevBuf x_, b_, d_, r_, z_, p_, q_, xg_;
+    Two xlay_, last_lay_;
+    double cg_tol2_ = 1e-20;
+    int cg_max_ = 500;
+    std::vector<StepRecord> trace_;
+    SweepResult res_;
+    std::vector<std::vector<double>> psi1_guess_;
+    std::vector<Bond> psi1_bonds_;
+    double t0_ = 0;
+
+    void build_mpos();
+    Env trivial_env(const Bond& bra, const Bond& ket) const;
+    void env_left(Env& out, const Env& L, const Site& Abra, const Site& Aket, const MPO& m, int i);
+    void env_right(Env& out, const Env& R, const Site& Abra, const Site& Aket, const MPO& m, int i);
+    void build_effop(EffOp& op, const Env& L, const Env& R, const TwoOp& O, const Two& ket,
+                     const double* xket, const Two& bra, double* ybra);
+    void build_diag(const Env& L, const Env& R, const TwoOp& O, const Two& lay, double* d, double shift);
+    void contract_sites(const Site& A, const Site& B, const Two& lay, double* out);
+    double truncate(int i, bool forward, const Two& lay, const double* x, int M, Site& C);
+    void next_guess(int i, bool forward, Site& C);
+    int solve(int i, double& e2);
+    void upd_left(int i);
+    void upd_right(int i);
+    double e3_final(int window);
+    void load_site(Site& s, const std::vector<double>& dense);
+};
+
+}  // namespace mpspt

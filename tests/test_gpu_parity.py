@@ -1,0 +1,176 @@
+"""Parity of the HIP MPS-PT path (through the C ABI) with the CPU oracle.
+
+* 4 active + 4 virtual orbitals (exact Psi0): at M1 = 64 the sweep must reach
+  the exact uncontracted E2/E3 of the determinant-space solve; at M1 = 16, 8
+  and 4 every running E2, every bond sector table, E3 and the final Psi1
+  (contracted to a determinant-space vector) must match the oracle's
+  same-algorithm sweep.
+* 8 active + 16 virtual orbitals (Psi0 compressed to M0 = 64, M1 = 128, four
+  sweeps; the benchmarked workload): E2 per sweep and E3 against stored
+  values written by tests/golden/make_golden.py from the oracle, the final
+  bond tables exactly, and the Hylleraas upper bound against the exact E2.
+Tolerances: 1e-9 Eh on the small system (both sides FP64, same algorithm,
+CG to 1e-10 relative residual); 1e-6 Eh on the large one.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+from oracle import exact, fock, mps
+from paper_1408_5092_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "c2_8a16v_seed0.json")
+
+
+@pytest.fixture(scope="module")
+def mp():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("needs a GPU")
+    from paper_1408_5092_amd import mpspt
+    mpspt.load_library()  # fails loudly when the HIP library is missing
+    return mpspt
+
+
+@pytest.fixture(scope="module")
+def c1():
+    ints = inputs.integrals(4, 4, 16, 0)
+    eri = fock.eri_from_cholesky(ints.B)
+    _, c, ab = exact.active_ground_state(ints.h, eri, 4, 4, 0)
+    ref = exact.brute_force(ints.h, eri, 4, ints.eps_virt, 4, 0, c, ab)
+    return ints, eri, exact.psi0_mps(c, ab, 4), ref
+
+
+def run_gpu(mp, ints, n_elec, psi0, guess, M1, **kw):
+    ctx = mp.Context(0)
+    ctx.load_integrals(ints.k_a, ints.k_v, ints.h, ints.B)
+    ctx.load_h0_partition(ints.eps_virt)
+    ctx.load_psi0(n_elec, 0, *psi0)
+    ctx.load_psi1_guess(guess.bonds, guess.sites)
+    res = ctx.sweep(M1, **kw)
+    return ctx, res
+
+
+def state_vector(sites):
+    v = sites[0]
+    for a in sites[1:]:
+        v = np.tensordot(v, a, axes=([-1], [0]))
+    return v.reshape(-1)
+
+
+def test_full_bond_dimension_reaches_exact(mp, c1):
+    ints, eri, psi0, ref = c1
+    print("case: 4a+4v M1=64 seed 0", flush=True)
+    g = inputs.psi1_guess(4, 4, 4, 0, 64, 1000)
+    ctx, res = run_gpu(mp, ints, 4, psi0, g, 64)
+    assert res["e0"] == pytest.approx(ref.E0, abs=1e-12)
+    assert res["e2"] == pytest.approx(ref.E2, abs=1e-9)
+    assert res["e3"] == pytest.approx(ref.E3, abs=1e-9)
+
+
+@pytest.mark.parametrize("M1", [16, 8, 4])
+def test_same_algorithm_parity(mp, c1, M1):
+    ints, eri, psi0, ref = c1
+    print(f"case: 4a+4v M1={M1} seed 0", flush=True)
+    g = inputs.psi1_guess(4, 4, 4, 0, M1, 1000)
+    ctx, res = run_gpu(mp, ints, 4, psi0, g, M1)
+    sw = mps.Sweeper(ints.h, eri, 4, ints.eps_virt, 4, 0, psi0, (g.bonds, g.sites), M1)
+    sw.run()
+    tr = ctx.get_trace()
+    oref = np.array([t["e2"] for t in sw.trace])
+    assert len(tr["e2"]) == len(oref)
+    np.testing.assert_allclose(tr["e2"], oref, rtol=0, atol=1e-9)
+    np.testing.assert_allclose(tr["discarded"], [t["discarded"] for t in sw.trace], rtol=0, atol=1e-9)
+    assert res["e2"] >= ref.E2 - 1e-10                 # Hylleraas upper bound
+    assert res["e3"] == pytest.approx(sw.e3(), abs=1e-9)
+    for b, ob in enumerate(sw.bonds()):
+        assert ctx.get_bond(0, b) == [(tuple(q), d) for q, d in ob], f"bond {b}"
+    vg = state_vector([ctx.get_site(0, i) for i in range(8)])
+    vo = state_vector(sw.A)
+    assert np.abs(vg - vo).max() < 1e-8 * np.abs(vo).max()
+
+
+def test_seeds_and_spin_sectors(mp):
+    """Other seeds and an open-shell reference (5 electrons, 2Sz = 1)."""
+    for (ka, kv, ne, tsz, seed, M1) in ((4, 4, 4, 0, 3, 12), (4, 3, 5, 1, 4, 10)):
+        print(f"case: {ka}a+{kv}v N={ne} 2Sz={tsz} seed {seed} M1={M1}", flush=True)
+        ints = inputs.integrals(ka, kv, 12, seed)
+        eri = fock.eri_from_cholesky(ints.B)
+        _, c, ab = exact.active_ground_state(ints.h, eri, ka, ne, tsz)
+        psi0 = exact.psi0_mps(c, ab, ka)
+        g = inputs.random_mps(ka + kv, ka, ne, tsz, (1, 2), M1, seed + 1000)
+        ctx = mp.Context(0)
+        ctx.load_integrals(ka, kv, ints.h, ints.B)
+        ctx.load_h0_partition(ints.eps_virt)
+        ctx.load_psi0(ne, tsz, *psi0)
+        ctx.load_psi1_guess(g.bonds, g.sites)
+        res = ctx.sweep(M1)
+        sw = mps.Sweeper(ints.h, eri, ka, ints.eps_virt, ne, tsz, psi0, (g.bonds, g.sites), M1)
+        sw.run()
+        np.testing.assert_allclose(ctx.get_trace()["e2"], [t["e2"] for t in sw.trace], rtol=0, atol=1e-9)
+        assert res["e3"] == pytest.approx(sw.e3(), abs=1e-9)
+
+
+def test_errors_are_reported(mp, c1):
+    ints, eri, psi0, ref = c1
+    ctx = mp.Context(0)
+    with pytest.raises(mp.MPSPTError) as e:
+        ctx.sweep(16)
+    assert e.value.status == -6  # MPSPT_E_STATE
+    ctx.load_integrals(4, 4, ints.h, ints.B)
+    ctx.load_h0_partition(ints.eps_virt)
+    bonds, sites = psi0
+    bad = [s.copy() for s in sites]
+    assert tuple(bonds[1][0][0]) == (0, 0) and tuple(bonds[2][0][0]) == (0, 0)
+    bad[1][0, 1, 0] = 1.0  # (0,0) + up electron cannot reach the (0,0) state: outside every block
+    with pytest.raises(mp.MPSPTError) as e:
+        ctx.load_psi0(4, 0, bonds, bad)
+    assert e.value.status == -2  # MPSPT_E_QN
+    # an indefinite zeroth-order operator is detected by CG (p.Ap <= 0)
+    ctx2 = mp.Context(0)
+    ctx2.load_integrals(4, 4, ints.h, ints.B)
+    ctx2.load_h0_partition(np.full(4, -5.0))
+    ctx2.load_psi0(4, 0, *psi0)
+    g = inputs.psi1_guess(4, 4, 4, 0, 16, 1000)
+    ctx2.load_psi1_guess(g.bonds, g.sites)
+    with pytest.raises(mp.MPSPTError) as e:
+        ctx2.sweep(16)
+    assert e.value.status == -5  # MPSPT_E_INDEFINITE
+
+
+def test_deterministic(mp, c1):
+    ints, eri, psi0, ref = c1
+    g = inputs.psi1_guess(4, 4, 4, 0, 16, 1000)
+    a = run_gpu(mp, ints, 4, psi0, g, 16)[0].get_trace()["e2"]
+    b = run_gpu(mp, ints, 4, psi0, g, 16)[0].get_trace()["e2"]
+    assert np.array_equal(a, b)
+
+
+@pytest.mark.skipif(not os.path.exists(GOLDEN), reason="golden values not generated")
+def test_benchmark_workload_against_stored_oracle():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("needs a GPU")
+    from paper_1408_5092_amd import mpspt as mp
+    gold = json.load(open(GOLDEN))
+    ka, kv, ne = gold["k_a"], gold["k_v"], gold["n_elec"]
+    print(f"case: {ka}a+{kv}v M0={gold['M0']} M1={gold['M1']} sweeps={gold['sweeps']} seed {gold['seed']}",
+          flush=True)
+    ints = inputs.integrals(ka, kv, gold["rank"], gold["seed"])
+    eri = fock.eri_from_cholesky(ints.B)
+    _, c, ab = exact.active_ground_state(ints.h, eri, ka, ne, 0)
+    psi0 = exact.psi0_mps(c, ab, ka, gold["M0"])
+    g = inputs.psi1_guess(ka, kv, ne, 0, gold["M1"], gold["psi1_seed"])
+    ctx, res = run_gpu(mp, ints, ne, psi0, g, gold["M1"], n_sweeps=gold["sweeps"])
+    assert res["e0"] == pytest.approx(gold["e0"], abs=1e-10)
+    np.testing.assert_allclose(res["e2_sweep"], gold["e2_sweep"], rtol=0, atol=1e-6)
+    assert res["e3"] == pytest.approx(gold["e3"], abs=1e-6)
+    tr = ctx.get_trace()["e2"]
+    np.testing.assert_allclose(tr, [t["e2"] for t in gold["trace"]], rtol=0, atol=1e-6)
+    assert res["e2"] >= gold["e2_exact"] - 1e-10
+    for b, ob in enumerate(gold["bonds"]):
+        assert ctx.get_bond(0, b) == [((n, s), d) for n, s, d in ob], f"bond {b}"
