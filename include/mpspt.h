@@ -81,6 +81,16 @@ mpspt_status mpspt_load_h0_partition(mpspt_ctx *ctx, int32_t kind, const double 
  * label is not (n_elec, two_sz). */
 mpspt_status mpspt_load_psi0(mpspt_ctx *ctx, int32_t n_elec, int32_t two_sz, const int32_t *bond_dims,
                              const int32_t *bond_qn, const double *const *site);
+/* Reference state from the library itself: two-site DMRG (Davidson local
+ * eigensolver, same kernels as the sweep) for the lowest state of the
+ * active-space Hamiltonian in (n_elec, two_sz) at bond dimension M0, started
+ * from the guess MPS given in mpspt_load_psi0's layout (k_a sites).  The
+ * result is loaded as Psi0 exactly as mpspt_load_psi0 would; *e_out receives
+ * the final Ritz value.  n_sweeps > 0 runs that many sweeps, 0 runs until
+ * the energy changes by less than e_tol.  Errors as mpspt_load_psi0. */
+mpspt_status mpspt_ground_state(mpspt_ctx *ctx, int32_t n_elec, int32_t two_sz, const int32_t *bond_dims,
+                                const int32_t *bond_qn, const double *const *site, int32_t M0,
+                                int32_t n_sweeps, double e_tol, double *e_out);
 /* Starting first-order MPS on all k_a + k_v sites (same layout), restricted to
  * one or two electrons in virtual orbitals.  Required before mpspt_sweep. */
 mpspt_status mpspt_load_psi1_guess(mpspt_ctx *ctx, const int32_t *bond_dims, const int32_t *bond_qn,
@@ -115,6 +125,17 @@ typedef struct {
 /* Run the sweep.  Errors: MPSPT_E_STATE if integrals, partition, Psi0 or the
  * Psi1 guess are missing; MPSPT_E_INDEFINITE if CG meets p.Ap <= 0. */
 mpspt_status mpspt_sweep(mpspt_ctx *ctx, const mpspt_sweep_params *params, mpspt_result *out);
+
+/* Kernel timing: enable = 1 starts recording HIP events around every launch
+ * on the context's stream (counters reset), 0 stops.  mpspt_kernel_stats
+ * returns, for kind 0 = grouped GEMM (k_gemm_grouped), 1 = grouped block
+ * axpy, 2 = Jacobi eigensolver, 3 = Jacobi diagonal, the summed event time,
+ * launch count and the algorithmic flops / bytes of those launches (flops
+ * 2mnk per block product; bytes: every operand block read once and every
+ * output block written once).  Waits for outstanding launches. */
+mpspt_status mpspt_profile(mpspt_ctx *ctx, int32_t enable);
+mpspt_status mpspt_kernel_stats(mpspt_ctx *ctx, int32_t kind, double *seconds, int64_t *launches,
+                                double *flops, double *bytes);
 
 /* Per local solve of the last mpspt_sweep: running E2, CG iterations,
  * discarded weight, seconds since the sweep started.  Up to cap entries;

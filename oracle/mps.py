@@ -115,31 +115,50 @@ def diag_two_site(L, R, W1, W2):
     return out
 
 
-def pcg(apply_A, rhs, diag, x0, tol, maxit):
-    """Jacobi-preconditioned CG for A x = rhs.  Returns (x, iterations, converged)."""
-    x = x0.copy()
-    r = rhs - apply_A(x)
+def pcg(apply_A, rhs, diag, x0, tol, maxit, restarts=3):
+    """Jacobi-preconditioned CG for A x = rhs (A positive definite).
+
+    The start vector is first scaled to the best multiple of itself
+    (alpha = x0.rhs / x0.A x0), and convergence is always confirmed on the
+    true residual rhs - A x; if the recursively updated residual drifted, CG
+    restarts from the current x.  Returns (x, iterations, converged, A x)."""
     nb = np.linalg.norm(rhs)
     if nb == 0.0:
-        return np.zeros_like(x), 0, True
-    z = r / diag
-    p = z.copy()
-    rz = np.vdot(r, z)
-    for it in range(maxit):
+        return np.zeros_like(x0), 0, True, np.zeros_like(x0)
+    x = x0.copy()
+    q = apply_A(x)
+    xq = np.vdot(x, q)
+    if xq > 0.0:
+        a = np.vdot(x, rhs) / xq
+        x *= a
+        q *= a
+    it = 0
+    for _ in range(restarts + 1):
+        r = rhs - q
         if np.linalg.norm(r) <= tol * nb:
-            return x, it, True
-        q = apply_A(p)
-        pq = np.vdot(p, q)
-        if pq <= 0.0:
-            raise FloatingPointError("H0 - E0 is not positive definite on the local space")
-        alpha = rz / pq
-        x += alpha * p
-        r -= alpha * q
+            return x, it, True, q
         z = r / diag
-        rz_new = np.vdot(r, z)
-        p = z + (rz_new / rz) * p
-        rz = rz_new
-    return x, maxit, np.linalg.norm(r) <= tol * nb
+        p = z.copy()
+        rz = np.vdot(r, z)
+        while it < maxit:
+            w = apply_A(p)
+            pw = np.vdot(p, w)
+            if pw <= 0.0:
+                raise FloatingPointError("H0 - E0 is not positive definite on the local space")
+            alpha = rz / pw
+            x += alpha * p
+            r -= alpha * w
+            it += 1
+            if np.linalg.norm(r) <= tol * nb:
+                break
+            z = r / diag
+            rz_new = np.vdot(r, z)
+            p = z + (rz_new / rz) * p
+            rz = rz_new
+        q = apply_A(x)
+        if it >= maxit:
+            break
+    return x, it, np.linalg.norm(rhs - q) <= tol * nb, q
 
 
 class Sweeper:
@@ -271,8 +290,8 @@ class Sweeper:
         def A(v):
             return (apply_two_site(L, R, m0.W[i], m0.W[i + 1], v, m0.dims[i + 1]) - self.E0 * v) * mask
 
-        x, it, conv = pcg(A, -b, d, x0 * mask, self.cg_tol, self.cg_maxit)
-        e = float(np.vdot(x, A(x)) + 2.0 * np.vdot(x, b))
+        x, it, conv, ax = pcg(A, -b, d, x0 * mask, self.cg_tol, self.cg_maxit)
+        e = float(np.vdot(x, ax) + 2.0 * np.vdot(x, b))
         return x, e, it, conv
 
     # ---------------------------------------------------------------- sweep

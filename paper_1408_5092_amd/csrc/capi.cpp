@@ -171,6 +171,21 @@ mpspt_status mpspt_load_psi0(mpspt_ctx* ctx, int32_t n_elec, int32_t two_sz, con
     });
 }
 
+mpspt_status mpspt_ground_state(mpspt_ctx* ctx, int32_t n_elec, int32_t two_sz, const int32_t* bond_dims,
+                                const int32_t* bond_qn, const double* const* site, int32_t M0, int32_t n_sweeps,
+                                double e_tol, double* e_out) {
+    if (!ctx) return MPSPT_E_ARG;
+    return guard(ctx, [&] {
+        if (!ctx->eng.have_part) throw mpspt::dev::Error{MPSPT_E_STATE, "load integrals and the H0 partition first"};
+        if (n_sweeps < 0 || n_sweeps > 64) throw argerr("n_sweeps must be in [0, 64]");
+        int ka = ctx->eng.k_a();
+        auto b = read_bonds(ka + 1, bond_dims, bond_qn);
+        double e = ctx->eng.ground_state(n_elec, two_sz, b, read_sites(b, site), M0, n_sweeps,
+                                         e_tol > 0 ? e_tol : 1e-10);
+        if (e_out) *e_out = e;
+    });
+}
+
 mpspt_status mpspt_load_psi1_guess(mpspt_ctx* ctx, const int32_t* bond_dims, const int32_t* bond_qn,
                                    const double* const* site) {
     if (!ctx) return MPSPT_E_ARG;
@@ -209,6 +224,24 @@ mpspt_status mpspt_sweep(mpspt_ctx* ctx, const mpspt_sweep_params* params, mpspt
         out->sigma_bytes = r.bytes;
         out->t_total_s = r.t_total;
         out->flags = r.flags;
+    });
+}
+
+mpspt_status mpspt_profile(mpspt_ctx* ctx, int32_t enable) {
+    if (!ctx) return MPSPT_E_ARG;
+    return guard(ctx, [&] { mpspt::dev::profile_enable(enable != 0); });
+}
+
+mpspt_status mpspt_kernel_stats(mpspt_ctx* ctx, int32_t kind, double* seconds, int64_t* launches, double* flops,
+                                double* bytes) {
+    if (!ctx) return MPSPT_E_ARG;
+    return guard(ctx, [&] {
+        if (kind < 0 || kind >= mpspt::dev::K_COUNT) throw argerr("unknown kernel kind");
+        mpspt::dev::KernelStats s = mpspt::dev::profile_stats(kind);
+        if (seconds) *seconds = s.seconds;
+        if (launches) *launches = s.launches;
+        if (flops) *flops = s.flops;
+        if (bytes) *bytes = s.bytes;
     });
 }
 

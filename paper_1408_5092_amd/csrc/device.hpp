@@ -83,8 +83,20 @@ void zero(void* p, size_t bytes);
 void sync();
 double now();  // host seconds
 
-void gemm_grouped(const GemmGroup* groups, int ngroups, const GemmTerm* terms, int ntiles);
-void axpy_grouped(const AxpyGroup* groups, int ngroups, const AxpyTerm* terms);
+// flops / bytes: algorithmic work of the launch, used only by the profiler
+void gemm_grouped(const GemmGroup* groups, int ngroups, const GemmTerm* terms, int ntiles, double flops = 0,
+                  double bytes = 0);
+void axpy_grouped(const AxpyGroup* groups, int ngroups, const AxpyTerm* terms, double flops = 0,
+                  double bytes = 0);
+
+// Per-kernel timing with HIP events recorded on the library's stream.
+enum KernelKind { K_GEMM = 0, K_AXPY = 1, K_EIG = 2, K_DIAG = 3, K_VEC = 4, K_COUNT = 5 };
+struct KernelStats {
+    double seconds = 0, flops = 0, bytes = 0;
+    long long launches = 0;
+};
+void profile_enable(bool on);          // resets the counters
+KernelStats profile_stats(int kind);   // waits for outstanding launches
 void diag_grouped(const DiagGroup* groups, int ngroups, const DiagTerm* terms);
 void eig_batched(const EigJob* jobs, int njobs);
 
@@ -104,6 +116,8 @@ void cg_update(double* x, double* r, double* z, const double* p, const double* q
 void cg_direction(double* p, const double* z, size_t n, const double* scal, int rz_cur, int rz_new);
 // y = a x + b y
 void axpby(double* y, const double* x, double a, double b, size_t n);
+// t = r / (theta - d), with |theta - d| floored at 1e-8 (Davidson correction)
+void davidson_precond(double* t, const double* r, const double* d, double theta, size_t n);
 
 constexpr int kPartials = 512;  // size of the partials workspace (doubles)
 

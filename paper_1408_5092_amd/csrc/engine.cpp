@@ -166,6 +166,7 @@ void GemmBatch::group(double* C, int ldc, int m, int n, bool acc) {
     dev::GemmGroup g{C, ldc, m, n, (int)t_.size(), 0, acc ? 1 : 0, tiles_};
     tiles_ += ((m + kTile - 1) / kTile) * ((n + kTile - 1) / kTile);
     g_.push_back(g);
+    bytes_ += 8.0 * m * n * (acc ? 2 : 1);
 }
 void GemmBatch::term(const double* A, int lda, bool tA, const double* B, int ldb, bool tB, int k, double alpha) {
     dev::GemmGroup& g = g_.back();
@@ -173,6 +174,7 @@ void GemmBatch::term(const double* A, int lda, bool tA, const double* B, int ldb
     t_.push_back({A, B, alpha, lda, ldb, k, tA ? 1 : 0, tB ? 1 : 0});
     ++g.nterms;
     flops_ += 2.0 * g.m * g.n * k;
+    bytes_ += 8.0 * ((double)g.m * k + (double)k * g.n);
 }
 void GemmBatch::upload() {
     std::vector<dev::GemmGroup> keep;
@@ -184,17 +186,19 @@ void GemmBatch::upload() {
     dt_.upload(t_);
 }
 void GemmBatch::run() const {
-    if (tiles_ > 0) dev::gemm_grouped(dg_.p, (int)g_.size(), dt_.p, tiles_);
+    if (tiles_ > 0) dev::gemm_grouped(dg_.p, (int)g_.size(), dt_.p, tiles_, flops_, bytes_);
 }
 
 void AxpyBatch::group(double* dst, int ldd, int m, int n, bool acc) {
     g_.push_back({dst, ldd, m, n, (int)t_.size(), 0, acc ? 1 : 0, 0});
+    if (m > 0 && n > 0) bytes_ += 8.0 * m * n * (acc ? 2 : 1);
 }
 void AxpyBatch::term(const double* src, int lds, bool trans, double alpha) {
     dev::AxpyGroup& g = g_.back();
     t_.push_back({src, lds, trans ? 1 : 0, alpha});
     ++g.nterms;
     flops_ += 2.0 * g.m * g.n;
+    bytes_ += 8.0 * g.m * g.n;
 }
 void AxpyBatch::upload() {
     std::vector<dev::AxpyGroup> keep;
@@ -205,7 +209,7 @@ void AxpyBatch::upload() {
     dt_.upload(t_);
 }
 void AxpyBatch::run() const {
-    if (!g_.empty()) dev::axpy_grouped(dg_.p, (int)g_.size(), dt_.p);
+    if (!g_.empty()) dev::axpy_grouped(dg_.p, (int)g_.size(), dt_.p, flops_, bytes_);
 }
 
 // ------------------------------------------------------------- inputs
@@ -847,12 +851,12 @@ double Engine::truncate(int i, bool forward, const Two& lay, const double* x, in
 
 void Engine::upd_left(int i) {
     env_left(LH_[i + 1], LH_[i], A_[i], A_[i], mpo_h0_, i);
-    env_left(LV_[i + 1], LV_[i], A_[i], P0_[i], mpo_v_, i);
+    if (!gs_) env_left(LV_[i + 1], LV_[i], A_[i], P0_[i], mpo_v_, i);
 }
 
 void Engine::upd_right(int i) {
     env_right(RH_[i], RH_[i + 1], A_[i], A_[i], mpo_h0_, i);
-    env_right(RV_[i], RV_[i + 1], A_[i], P0_[i], mpo_v_, i);
+    if (!gs_) env_right(RV_[i], RV_[i + 1], A_[i], P0_[i], mpo_v_, i);
 }
 
 // ---------------------------------------------------------- local solve
@@ -878,23 +882,37 @@ int Engine::solve(int i, double& e2) {
         res_.bytes += sig.bytes;
     };
     double sc[dev::S_N];
+    // start from the best multiple of the guess: x0 <- a x0, a = -x0.b / x0.A x0
     dev::d2d(x_.p, xg_.p, n * sizeof(double));
     dev::d2d(p_.p, x_.p, n * sizeof(double));
     apply();
-    dev::cg_init(r_.p, z_.p, p_.p, b_.p, q_.p, d_.p, n, scal_.p, partials_.p);
+    dev::dot(x_.p, b_.p, n, scal_.p, dev::S_DOT, partials_.p);
     dev::d2h(sc, scal_.p, sizeof(sc));
-    const double bb = sc[dev::S_BB];
+    if (sc[dev::S_PQ] > 0.0) {
+        const double a = -sc[dev::S_DOT] / sc[dev::S_PQ];
+        dev::axpby(x_.p, x_.p, 0.0, a, n);
+        dev::axpby(q_.p, q_.p, 0.0, a, n);
+    }
     int it = 0;
-    if (bb == 0.0) {
-        dev::zero(x_.p, n * sizeof(double));
-    } else {
-        int cur = dev::S_RZ0, nxt = dev::S_RZ1;
+    // CG on A x = -b; convergence is confirmed on the true residual -b - A x
+    // and CG restarts from x when the updated residual has drifted.
+    for (int restart = 0; restart < 4; ++restart) {
+        dev::cg_init(r_.p, z_.p, p_.p, b_.p, q_.p, d_.p, n, scal_.p, partials_.p);
+        dev::d2h(sc, scal_.p, sizeof(sc));
+        const double bb = sc[dev::S_BB];
         double rr = sc[dev::S_RR];
-        while (rr > cg_tol2_ * bb) {
-            if (it >= cg_max_) {
-                res_.flags |= 1;
-                break;
-            }
+        if (bb == 0.0) {
+            dev::zero(x_.p, n * sizeof(double));
+            dev::zero(q_.p, n * sizeof(double));
+            break;
+        }
+        if (rr <= cg_tol2_ * bb) break;
+        if (it >= cg_max_) {
+            res_.flags |= 1;
+            break;
+        }
+        int cur = dev::S_RZ0, nxt = dev::S_RZ1;
+        while (it < cg_max_) {
             apply();
             dev::cg_update(x_.p, r_.p, z_.p, p_.p, q_.p, d_.p, n, scal_.p, cur, nxt, partials_.p);
             dev::d2h(sc, scal_.p, sizeof(sc));
@@ -906,10 +924,12 @@ int Engine::solve(int i, double& e2) {
             dev::cg_direction(p_.p, z_.p, n, scal_.p, cur, nxt);
             std::swap(cur, nxt);
         }
+        dev::d2d(p_.p, x_.p, n * sizeof(double));
+        apply();  // q = A x, scal[PQ] = x.A x
     }
-    // Hylleraas value of x: x.(A x) + 2 x.b
+    // Hylleraas value of x: x.(A x) + 2 x.b  (q = A x from the last application)
     dev::d2d(p_.p, x_.p, n * sizeof(double));
-    apply();
+    dev::cg_shift_dot(q_.p, p_.p, 0.0, n, scal_.p, partials_.p);
     dev::dot(x_.p, b_.p, n, scal_.p, dev::S_DOT, partials_.p);
     dev::d2h(sc, scal_.p, sizeof(sc));
     e2 = sc[dev::S_PQ] + 2.0 * sc[dev::S_DOT];
@@ -964,42 +984,38 @@ double Engine::e3_final(int window) {
     return sc[dev::S_DOT];
 }
 
-SweepResult Engine::sweep(const SweepParams& p) {
-    if (!have_psi1) throw err(MPSPT_E_STATE, "load integrals, the H0 partition, Psi0 and a Psi1 guess first");
-    if (p.M1 < 1) throw err(MPSPT_E_ARG, "M1 must be positive");
-    res_ = SweepResult();
-    res_.e0 = E0_;
-    trace_.clear();
-    cg_tol2_ = p.cg_rel_tol * p.cg_rel_tol;
-    cg_max_ = p.cg_max_iter;
-    dev::sync();
-    t0_ = dev::now();
+void Engine::start(const std::vector<Bond>& bonds, const std::vector<std::vector<double>>& sites, int M) {
     A_.clear();
     for (int i = 0; i < n_; ++i) {
-        A_.push_back(make_site(psi1_bonds_[i], psi1_bonds_[i + 1]));
-        load_site(A_[i], psi1_guess_[i]);
+        A_.push_back(make_site(bonds[i], bonds[i + 1]));
+        load_site(A_[i], sites[i]);
     }
     for (auto* v : {&LH_, &RH_, &LV_, &RV_}) {
         v->clear();
         v->resize(n_ + 1);
     }
     LH_[0] = trivial_env(A_[0].L, A_[0].L);
-    LV_[0] = trivial_env(A_[0].L, P0_[0].L);
     RH_[n_] = trivial_env(A_[n_ - 1].R, A_[n_ - 1].R);
-    RV_[n_] = trivial_env(A_[n_ - 1].R, P0_[n_ - 1].R);
+    if (!gs_) {
+        LV_[0] = trivial_env(A_[0].L, P0_[0].L);
+        RV_[n_] = trivial_env(A_[n_ - 1].R, P0_[n_ - 1].R);
+    }
     // right-canonical start: backward pass without solves
     for (int i = n_ - 2; i >= 0; --i) {
         Two lay = make_two(A_[i].L, A_[i + 1].R, &adm_[i + 1]);
         x_.ensure(std::max<size_t>(lay.size, 1));
         contract_sites(A_[i], A_[i + 1], lay, x_.p);
         Site C;
-        truncate(i, false, lay, x_.p, p.M1, C);
+        truncate(i, false, lay, x_.p, M, C);
         A_[i] = std::move(C);
         upd_right(i + 1);
     }
     xlay_ = make_two(A_[0].L, A_[1].R, &adm_[1]);
     xg_.ensure(std::max<size_t>(xlay_.size, 1));
     contract_sites(A_[0], A_[1], xlay_, xg_.p);
+}
+
+double Engine::run_sweeps(int M, int n_sweeps, int max_sweeps, double e_tol) {
     double e2 = 0;
     for (int sw = 0; sw < 64; ++sw) {
         double maxd = 0;
@@ -1007,11 +1023,11 @@ SweepResult Engine::sweep(const SweepParams& p) {
             const bool fwd = dir == 0;
             for (int k = 0; k < n_ - 1; ++k) {
                 const int i = fwd ? k : n_ - 2 - k;
-                int it = solve(i, e2);
+                int it = gs_ ? davidson(i, e2) : solve(i, e2);
                 res_.cg_iters += it;
                 last_lay_ = xlay_;
                 Site C;
-                double disc = truncate(i, fwd, xlay_, x_.p, p.M1, C);
+                double disc = truncate(i, fwd, xlay_, x_.p, M, C);
                 if (fwd) upd_left(i);
                 else upd_right(i + 1);
                 next_guess(i, fwd, C);
@@ -1024,19 +1040,223 @@ SweepResult Engine::sweep(const SweepParams& p) {
         res_.e2_sweep.push_back(e2);
         res_.n_sweeps = sw + 1;
         res_.max_disc = maxd;
-        if (p.n_sweeps > 0) {
-            if (res_.n_sweeps >= p.n_sweeps) break;
+        if (n_sweeps > 0) {
+            if (res_.n_sweeps >= n_sweeps) break;
         } else {
             size_t ns = res_.e2_sweep.size();
-            if (ns > 1 && std::fabs(res_.e2_sweep[ns - 1] - res_.e2_sweep[ns - 2]) < p.e_tol) break;
-            if (res_.n_sweeps >= p.max_sweeps) break;
+            if (ns > 1 && std::fabs(res_.e2_sweep[ns - 1] - res_.e2_sweep[ns - 2]) < e_tol) break;
+            if (res_.n_sweeps >= max_sweeps) break;
         }
     }
-    res_.e2 = e2;
+    return e2;
+}
+
+SweepResult Engine::sweep(const SweepParams& p) {
+    if (!have_psi1) throw err(MPSPT_E_STATE, "load integrals, the H0 partition, Psi0 and a Psi1 guess first");
+    if (p.M1 < 1) throw err(MPSPT_E_ARG, "M1 must be positive");
+    res_ = SweepResult();
+    res_.e0 = E0_;
+    trace_.clear();
+    cg_tol2_ = p.cg_rel_tol * p.cg_rel_tol;
+    cg_max_ = p.cg_max_iter;
+    dev::sync();
+    t0_ = dev::now();
+    start(psi1_bonds_, psi1_guess_, p.M1);
+    res_.e2 = run_sweeps(p.M1, p.n_sweeps, p.max_sweeps, p.e_tol);
     dev::sync();
     res_.t_total = dev::now() - t0_;
     if (p.compute_e3) res_.e3 = e3_final(0);
     return res_;
+}
+
+double Engine::ground_state(int n_elec, int two_sz, const std::vector<Bond>& bonds,
+                            const std::vector<std::vector<double>>& sites, int M0, int n_sweeps, double e_tol) {
+    if (!have_part) throw err(MPSPT_E_STATE, "load integrals and the H0 partition before the ground-state sweep");
+    if ((int)bonds.size() != k_a_ + 1 || (int)sites.size() != k_a_) throw err(MPSPT_E_ARG, "guess needs k_a sites");
+    if (k_a_ < 2) throw err(MPSPT_E_ARG, "the ground-state sweep needs at least two active orbitals");
+    if (M0 < 1) throw err(MPSPT_E_ARG, "M0 must be positive");
+    // admissible sectors of the active space alone
+    std::vector<std::set<std::pair<int, int>>> left(k_a_ + 1), right(k_a_ + 1);
+    left[0].insert({0, 0});
+    right[k_a_].insert({0, 0});
+    for (int i = 0; i < k_a_; ++i)
+        for (auto& t : left[i])
+            for (int s = 0; s < 4; ++s) left[i + 1].insert({t.first + site_dq(s).n, t.second + site_dq(s).s});
+    for (int i = k_a_ - 1; i >= 0; --i)
+        for (auto& t : right[i + 1])
+            for (int s = 0; s < 4; ++s) right[i].insert({t.first + site_dq(s).n, t.second + site_dq(s).s});
+    std::vector<std::set<QN>> adm(k_a_ + 1);
+    for (int b = 0; b <= k_a_; ++b)
+        for (auto& l : left[b])
+            if (right[b].count({n_elec - l.first, two_sz - l.second})) adm[b].insert(QN{l.first, l.second});
+    for (int b = 0; b <= k_a_; ++b)
+        for (auto& q : bonds[b].q)
+            if (!adm[b].count(q)) throw err(MPSPT_E_QN, "guess bond sector cannot reach the target (N, 2Sz)");
+    // run the sweep on the active sites with H_act, then load the result as Psi0
+    const int n_save = n_;
+    MPO h0_save = std::move(mpo_h0_);
+    std::vector<std::set<QN>> adm_save = std::move(adm_);
+    gs_ = true;
+    n_ = k_a_;
+    mpo_h0_ = build_mpo(OpKind::HAct, k_a_, k_v_, h_, eri_, eps_);
+    adm_ = adm;
+    res_ = SweepResult();
+    trace_.clear();
+    double e = 0;
+    std::vector<Bond> out_b;
+    std::vector<std::vector<double>> out_s;
+    try {
+        dev::sync();
+        t0_ = dev::now();
+        start(bonds, sites, M0);
+        e = run_sweeps(M0, n_sweeps, 64, e_tol);
+        for (int i = 0; i < n_; ++i) out_b.push_back(A_[i].L);
+        out_b.push_back(A_[n_ - 1].R);
+        for (int i = 0; i < n_; ++i) {
+            std::vector<double> v;
+            int Dl, Dr;
+            site_dense(0, i, v, Dl, Dr);
+            out_s.push_back(std::move(v));
+        }
+    } catch (...) {
+        gs_ = false;
+        n_ = n_save;
+        mpo_h0_ = std::move(h0_save);
+        adm_ = std::move(adm_save);
+        A_.clear();
+        throw;
+    }
+    gs_ = false;
+    n_ = n_save;
+    mpo_h0_ = std::move(h0_save);
+    adm_ = std::move(adm_save);
+    A_.clear();
+    gs_trace_ = trace_;
+    set_psi0(n_elec, two_sz, out_b, out_s);
+    return e;
+}
+
+// Lowest eigenpair of H_eff at window i by Davidson with the Jacobi
+// preconditioner; the normalised eigenvector is left in x_.
+int Engine::davidson(int i, double& e) {
+    const Two& lay = xlay_;
+    const size_t n = lay.size;
+    constexpr int kMax = 16;
+    for (DevBuf* b : {&x_, &d_, &r_, &z_, &p_, &q_}) b->ensure(std::max<size_t>(n, 1));
+    dav_V_.ensure(std::max<size_t>(n, 1) * kMax);
+    dav_AV_.ensure(std::max<size_t>(n, 1) * kMax);
+    partials_.ensure(dev::kPartials);
+    scal_.ensure(dev::S_N);
+    TwoOp O = make_twoop(mpo_h0_, i);
+    build_diag(LH_[i], RH_[i + 2], O, lay, d_.p, 0.0);
+    EffOp sig;
+    build_effop(sig, LH_[i], RH_[i + 2], O, lay, p_.p, lay, q_.p);
+    double sc[dev::S_N];
+    auto dotp = [&](const double* a, const double* b) {
+        dev::dot(a, b, n, scal_.p, dev::S_DOT, partials_.p);
+        dev::d2h(sc, scal_.p, sizeof(sc));
+        return sc[dev::S_DOT];
+    };
+    auto Vk = [&](int k) { return dav_V_.p + (size_t)k * n; };
+    auto AVk = [&](int k) { return dav_AV_.p + (size_t)k * n; };
+    auto applyA = [&](const double* v, double* out) {
+        dev::d2d(p_.p, v, n * sizeof(double));
+        sig.run();
+        dev::d2d(out, q_.p, n * sizeof(double));
+        res_.sigma_calls++;
+        res_.flops += sig.flops;
+        res_.bytes += sig.bytes;
+    };
+    // start from the guess
+    dev::d2d(Vk(0), xg_.p, n * sizeof(double));
+    double nrm = std::sqrt(dotp(Vk(0), Vk(0)));
+    if (!(nrm > 0)) throw err(MPSPT_E_STATE, "zero guess in the ground-state sweep");
+    dev::axpby(Vk(0), Vk(0), 0.0, 1.0 / nrm, n);
+    applyA(Vk(0), AVk(0));
+    std::vector<double> Hs(kMax * kMax, 0.0);
+    Hs[0] = dotp(Vk(0), AVk(0));
+    int m = 1, it = 0;
+    double theta = Hs[0];
+    std::vector<double> cvec(1, 1.0);
+    for (; it < cg_max_; ++it) {
+        // Ritz pair of the projected matrix (host, m <= 16)
+        std::vector<double> a(m * m), v(m * m, 0.0);
+        for (int r = 0; r < m; ++r)
+            for (int c = 0; c < m; ++c) a[r * m + c] = 0.5 * (Hs[r * kMax + c] + Hs[c * kMax + r]);
+        for (int r = 0; r < m; ++r) v[r * m + r] = 1.0;
+        for (int swp = 0; swp < 100; ++swp) {
+            double off = 0;
+            for (int r = 0; r < m; ++r)
+                for (int c = 0; c < m; ++c)
+                    if (r != c) off += a[r * m + c] * a[r * m + c];
+            if (off < 1e-30) break;
+            for (int pp = 0; pp < m; ++pp)
+                for (int qq = pp + 1; qq < m; ++qq) {
+                    double apq = a[pp * m + qq];
+                    if (apq == 0) continue;
+                    double tau = (a[qq * m + qq] - a[pp * m + pp]) / (2 * apq);
+                    double t = (tau >= 0 ? 1 : -1) / (std::fabs(tau) + std::sqrt(1 + tau * tau));
+                    double c = 1 / std::sqrt(1 + t * t), s = t * c;
+                    for (int j = 0; j < m; ++j) {
+                        double x1 = a[pp * m + j], x2 = a[qq * m + j];
+                        a[pp * m + j] = c * x1 - s * x2;
+                        a[qq * m + j] = s * x1 + c * x2;
+                    }
+                    for (int j = 0; j < m; ++j) {
+                        double x1 = a[j * m + pp], x2 = a[j * m + qq];
+                        a[j * m + pp] = c * x1 - s * x2;
+                        a[j * m + qq] = s * x1 + c * x2;
+                        double v1 = v[j * m + pp], v2 = v[j * m + qq];
+                        v[j * m + pp] = c * v1 - s * v2;
+                        v[j * m + qq] = s * v1 + c * v2;
+                    }
+                }
+        }
+        int lo = 0;
+        for (int r = 1; r < m; ++r)
+            if (a[r * m + r] < a[lo * m + lo]) lo = r;
+        theta = a[lo * m + lo];
+        cvec.assign(m, 0.0);
+        for (int r = 0; r < m; ++r) cvec[r] = v[r * m + lo];
+        // x = V c, Ax = AV c, residual r = Ax - theta x
+        dev::zero(x_.p, n * sizeof(double));
+        dev::zero(z_.p, n * sizeof(double));
+        for (int r = 0; r < m; ++r) {
+            dev::axpby(x_.p, Vk(r), cvec[r], 1.0, n);
+            dev::axpby(z_.p, AVk(r), cvec[r], 1.0, n);
+        }
+        dev::d2d(r_.p, z_.p, n * sizeof(double));
+        dev::axpby(r_.p, x_.p, -theta, 1.0, n);
+        double rn = std::sqrt(dotp(r_.p, r_.p));
+        if (rn < dav_tol_) break;
+        if (m == kMax) {  // restart from the current Ritz vector
+            dev::d2d(Vk(0), x_.p, n * sizeof(double));
+            dev::d2d(AVk(0), z_.p, n * sizeof(double));
+            Hs.assign(kMax * kMax, 0.0);
+            Hs[0] = theta;
+            m = 1;
+        }
+        // correction t = r / (theta - D), orthogonalised twice against V
+        dev::davidson_precond(Vk(m), r_.p, d_.p, theta, n);
+        for (int pass = 0; pass < 2; ++pass)
+            for (int r = 0; r < m; ++r) {
+                double ov = dotp(Vk(r), Vk(m));
+                dev::axpby(Vk(m), Vk(r), -ov, 1.0, n);
+            }
+        double tn = std::sqrt(dotp(Vk(m), Vk(m)));
+        if (!(tn > 1e-14)) break;
+        dev::axpby(Vk(m), Vk(m), 0.0, 1.0 / tn, n);
+        applyA(Vk(m), AVk(m));
+        for (int r = 0; r <= m; ++r) {
+            Hs[r * kMax + m] = dotp(Vk(r), AVk(m));
+            Hs[m * kMax + r] = Hs[r * kMax + m];
+        }
+        ++m;
+    }
+    double xn = std::sqrt(dotp(x_.p, x_.p));
+    dev::axpby(x_.p, x_.p, 0.0, 1.0 / xn, n);
+    e = theta;
+    return it;
 }
 
 const Bond& Engine::bond(int which, int b) const {

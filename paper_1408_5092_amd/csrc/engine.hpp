@@ -122,13 +122,14 @@ TwoOp make_twoop(const MPO& m, int i);
 // Work list of grouped GEMMs, reusable across launches.
 class GemmBatch {
   public:
-    void clear() { g_.clear(); t_.clear(); tiles_ = 0; flops_ = 0; }
+    void clear() { g_.clear(); t_.clear(); tiles_ = 0; flops_ = 0; bytes_ = 0; }
     void group(double* C, int ldc, int m, int n, bool acc);
     void term(const double* A, int lda, bool tA, const double* B, int ldb, bool tB, int k, double alpha);
     void upload();
     void run() const;
     bool empty() const { return g_.empty(); }
     double flops() const { return flops_; }
+    double bytes() const { return bytes_; }  // operand blocks read once, output blocks written once
     size_t nterms() const { return t_.size(); }
 
   private:
@@ -137,25 +138,26 @@ class GemmBatch {
     DevArr<dev::GemmGroup> dg_;
     DevArr<dev::GemmTerm> dt_;
     int tiles_ = 0;
-    double flops_ = 0;
+    double flops_ = 0, bytes_ = 0;
 };
 
 class AxpyBatch {
   public:
-    void clear() { g_.clear(); t_.clear(); flops_ = 0; }
+    void clear() { g_.clear(); t_.clear(); flops_ = 0; bytes_ = 0; }
     void group(double* dst, int ldd, int m, int n, bool acc);
     void term(const double* src, int lds, bool trans, double alpha);
     void upload();
     void run() const;
     bool empty() const { return g_.empty(); }
     double flops() const { return flops_; }
+    double bytes() const { return bytes_; }
 
   private:
     std::vector<dev::AxpyGroup> g_;
     std::vector<dev::AxpyTerm> t_;
     DevArr<dev::AxpyGroup> dg_;
     DevArr<dev::AxpyTerm> dt_;
-    double flops_ = 0;
+    double flops_ = 0, bytes_ = 0;
 };
 
 // y = sum L (x) O (x) R applied to x (three grouped launches).
@@ -193,6 +195,10 @@ class Engine {
     void set_psi0(int n_elec, int two_sz, const std::vector<Bond>& bonds, const std::vector<std::vector<double>>& sites);
     void set_psi1(const std::vector<Bond>& bonds, const std::vector<std::vector<double>>& sites);
     SweepResult sweep(const SweepParams& p);
+    // Two-site DMRG for the lowest state of H_act in (n_elec, two_sz) on the
+    // active sites, from a guess MPS; the result is loaded as Psi0.
+    double ground_state(int n_elec, int two_sz, const std::vector<Bond>& bonds,
+                        const std::vector<std::vector<double>>& sites, int M0, int n_sweeps, double e_tol);
 
     const std::vector<StepRecord>& trace() const { return trace_; }
     const Bond& bond(int which, int b) const;
@@ -228,6 +234,10 @@ class Engine {
     std::vector<std::vector<double>> psi1_guess_;
     std::vector<Bond> psi1_bonds_;
     double t0_ = 0;
+    bool gs_ = false;            // ground-state sweep (Davidson) instead of the linear solve
+    double dav_tol_ = 1e-9;
+    DevBuf dav_V_, dav_AV_;
+    std::vector<StepRecord> gs_trace_;
 
     void build_mpos();
     Env trivial_env(const Bond& bra, const Bond& ket) const;
@@ -240,6 +250,9 @@ class Engine {
     double truncate(int i, bool forward, const Two& lay, const double* x, int M, Site& C);
     void next_guess(int i, bool forward, Site& C);
     int solve(int i, double& e2);
+    int davidson(int i, double& e);
+    void start(const std::vector<Bond>& bonds, const std::vector<std::vector<double>>& sites, int M);
+    double run_sweeps(int M, int n_sweeps, int max_sweeps, double e_tol);
     void upd_left(int i);
     void upd_right(int i);
     double e3_final(int window);

@@ -14,6 +14,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstdio>
+#include <vector>
 
 #include "../../include/mpspt.h"
 #include "device.hpp"
@@ -357,6 +358,15 @@ __global__ __launch_bounds__(RED_THREADS) void k_axpby(double* y, const double* 
         y[e] = a * x[e] + b * y[e];
 }
 
+__global__ __launch_bounds__(RED_THREADS) void k_dav_precond(double* t, const double* r, const double* d,
+                                                             double theta, size_t n) {
+    for (size_t e = (size_t)blockIdx.x * RED_THREADS + threadIdx.x; e < n; e += (size_t)gridDim.x * RED_THREADS) {
+        double den = theta - d[e];
+        if (fabs(den) < 1e-8) den = den < 0 ? -1e-8 : 1e-8;
+        t[e] = r[e] / den;
+    }
+}
+
 }  // namespace
 
 // ------------------------------------------------------------ host side
@@ -410,23 +420,98 @@ double now() {
     return duration<double>(steady_clock::now().time_since_epoch()).count();
 }
 
-void gemm_grouped(const GemmGroup* groups, int ngroups, const GemmTerm* terms, int ntiles) {
+// ------------------------------------------------------------ profiling
+namespace {
+struct ProfRec {
+    int kind;
+    hipEvent_t a, b;
+    double flops, bytes;
+};
+bool g_prof = false;
+std::vector<ProfRec> g_pending;
+std::vector<hipEvent_t> g_event_pool;
+KernelStats g_stats[K_COUNT];
+
+hipEvent_t take_event() {
+    if (!g_event_pool.empty()) {
+        hipEvent_t e = g_event_pool.back();
+        g_event_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e;
+    check(hipEventCreate(&e), "hipEventCreate");
+    return e;
+}
+
+void prof_flush() {
+    if (g_pending.empty()) return;
+    check(hipEventSynchronize(g_pending.back().b), "hipEventSynchronize");
+    for (auto& r : g_pending) {
+        float ms = 0;
+        check(hipEventElapsedTime(&ms, r.a, r.b), "hipEventElapsedTime");
+        KernelStats& s = g_stats[r.kind];
+        s.seconds += ms * 1e-3;
+        s.flops += r.flops;
+        s.bytes += r.bytes;
+        s.launches++;
+        g_event_pool.push_back(r.a);
+        g_event_pool.push_back(r.b);
+    }
+    g_pending.clear();
+}
+
+// Records events around one launch when profiling is on.
+struct Prof {
+    ProfRec r;
+    bool on;
+    Prof(int kind, double flops, double bytes) : on(g_prof) {
+        if (!on) return;
+        r = {kind, take_event(), take_event(), flops, bytes};
+        check(hipEventRecord(r.a, g_stream), "hipEventRecord");
+    }
+    ~Prof() noexcept(false) {
+        if (!on) return;
+        check(hipEventRecord(r.b, g_stream), "hipEventRecord");
+        g_pending.push_back(r);
+        if (g_pending.size() >= 4096) prof_flush();
+    }
+};
+}  // namespace
+
+void profile_enable(bool on) {
+    if (g_prof) prof_flush();
+    g_prof = on;
+    for (auto& s : g_stats) s = KernelStats();
+}
+
+KernelStats profile_stats(int kind) {
+    prof_flush();
+    if (kind < 0 || kind >= K_COUNT) return KernelStats();
+    return g_stats[kind];
+}
+
+void gemm_grouped(const GemmGroup* groups, int ngroups, const GemmTerm* terms, int ntiles, double flops,
+                  double bytes) {
     if (ntiles <= 0) return;
+    Prof p(K_GEMM, flops, bytes);
     hipLaunchKernelGGL(k_gemm_grouped, dim3(ntiles), dim3(256), 0, g_stream, groups, ngroups, terms);
     check(hipGetLastError(), "k_gemm_grouped");
 }
-void axpy_grouped(const AxpyGroup* groups, int ngroups, const AxpyTerm* terms) {
+void axpy_grouped(const AxpyGroup* groups, int ngroups, const AxpyTerm* terms, double flops, double bytes) {
     if (ngroups <= 0) return;
+    Prof p(K_AXPY, flops, bytes);
     hipLaunchKernelGGL(k_axpy_grouped, dim3(ngroups), dim3(256), 0, g_stream, groups, terms);
     check(hipGetLastError(), "k_axpy_grouped");
 }
 void diag_grouped(const DiagGroup* groups, int ngroups, const DiagTerm* terms) {
     if (ngroups <= 0) return;
+    Prof p(K_DIAG, 0, 0);
     hipLaunchKernelGGL(k_diag_grouped, dim3(ngroups), dim3(256), 0, g_stream, groups, terms);
     check(hipGetLastError(), "k_diag_grouped");
 }
 void eig_batched(const EigJob* jobs, int njobs) {
     if (njobs <= 0) return;
+    Prof p(K_EIG, 0, 0);
     hipLaunchKernelGGL(k_eig_jacobi, dim3(njobs), dim3(256), 0, g_stream, jobs);
     check(hipGetLastError(), "k_eig_jacobi");
 }
@@ -468,6 +553,12 @@ void cg_direction(double* p, const double* z, size_t n, const double* scal, int 
     const int nb = n_blocks(n);
     hipLaunchKernelGGL(k_cg_direction, dim3(nb), dim3(RED_THREADS), 0, g_stream, p, z, n, scal, rz_cur, rz_new);
     check(hipGetLastError(), "cg_direction");
+}
+void davidson_precond(double* t, const double* r, const double* d, double theta, size_t n) {
+    if (!n) return;
+    const int nb = n_blocks(n);
+    hipLaunchKernelGGL(k_dav_precond, dim3(nb), dim3(RED_THREADS), 0, g_stream, t, r, d, theta, n);
+    check(hipGetLastError(), "davidson_precond");
 }
 void axpby(double* y, const double* x, double a, double b, size_t n) {
     if (!n) return;

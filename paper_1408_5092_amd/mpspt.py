@@ -19,7 +19,8 @@ STATUS = {0: "MPSPT_OK", -1: "MPSPT_E_ARG", -2: "MPSPT_E_QN", -3: "MPSPT_E_NOMEM
 
 EXPORTED = ["mpspt_create", "mpspt_destroy", "mpspt_last_error", "mpspt_load_integrals",
             "mpspt_load_integrals_eri", "mpspt_load_h0_partition", "mpspt_load_psi0",
-            "mpspt_load_psi1_guess", "mpspt_sweep", "mpspt_get_trace", "mpspt_get_bond",
+            "mpspt_load_psi1_guess", "mpspt_ground_state", "mpspt_sweep", "mpspt_profile",
+            "mpspt_kernel_stats", "mpspt_get_trace", "mpspt_get_bond",
             "mpspt_get_site", "mpspt_mpo_dense", "mpspt_mpo_dims"]
 
 
@@ -68,6 +69,9 @@ def load_library(path: str | None = None):
     lib.mpspt_load_h0_partition.argtypes = [P, I, dp]
     lib.mpspt_load_psi0.argtypes = [P, I, I, ip, ip, C.POINTER(dp)]
     lib.mpspt_load_psi1_guess.argtypes = [P, ip, ip, C.POINTER(dp)]
+    lib.mpspt_ground_state.argtypes = [P, I, I, ip, ip, C.POINTER(dp), I, I, D, dp]
+    lib.mpspt_profile.argtypes = [P, I]
+    lib.mpspt_kernel_stats.argtypes = [P, I, dp, C.POINTER(C.c_int64), dp, dp]
     lib.mpspt_sweep.argtypes = [P, C.POINTER(SweepParams), C.POINTER(Result)]
     lib.mpspt_get_trace.argtypes = [P, I, dp, ip, dp, dp, ip]
     lib.mpspt_get_bond.argtypes = [P, I, I, I, ip, ip]
@@ -160,6 +164,14 @@ class Context:
         self._ok(self.lib.mpspt_load_psi0(self.h, n_elec, two_sz, dims.ctypes.data_as(C.POINTER(C.c_int32)),
                                           qn.ctypes.data_as(C.POINTER(C.c_int32)), ptrs))
 
+    def ground_state(self, n_elec, two_sz, bonds, sites, M0, n_sweeps=0, e_tol=1e-10):
+        dims, qn, keep, ptrs = _mps_args(bonds, sites)
+        e = C.c_double()
+        self._ok(self.lib.mpspt_ground_state(self.h, n_elec, two_sz, dims.ctypes.data_as(C.POINTER(C.c_int32)),
+                                             qn.ctypes.data_as(C.POINTER(C.c_int32)), ptrs, M0, n_sweeps, e_tol,
+                                             C.byref(e)))
+        return e.value
+
     def load_psi1_guess(self, bonds, sites):
         dims, qn, keep, ptrs = _mps_args(bonds, sites)
         self._ok(self.lib.mpspt_load_psi1_guess(self.h, dims.ctypes.data_as(C.POINTER(C.c_int32)),
@@ -173,6 +185,17 @@ class Context:
         out = {f: getattr(r, f) for f, _ in Result._fields_}
         out["e2_sweep"] = list(r.e2_sweep)[:r.n_sweeps_done]
         return out
+
+    def profile(self, enable=True):
+        self._ok(self.lib.mpspt_profile(self.h, int(bool(enable))))
+
+    KERNELS = {0: "k_gemm_grouped", 1: "k_axpy_grouped", 2: "k_eig_jacobi", 3: "k_diag_grouped"}
+
+    def kernel_stats(self, kind):
+        s, n, f, b = C.c_double(), C.c_int64(), C.c_double(), C.c_double()
+        self._ok(self.lib.mpspt_kernel_stats(self.h, kind, C.byref(s), C.byref(n), C.byref(f), C.byref(b)))
+        return dict(kernel=self.KERNELS.get(kind, str(kind)), seconds=s.value, launches=n.value, flops=f.value,
+                    bytes=b.value)
 
     def get_trace(self):
         n = C.c_int32()

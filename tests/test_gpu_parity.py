@@ -115,6 +115,38 @@ def test_seeds_and_spin_sectors(mp):
         assert res["e3"] == pytest.approx(sw.e3(), abs=1e-9)
 
 
+def test_ground_state_reference(mp, c1):
+    """The library's own Psi0 (two-site DMRG with Davidson): exact at a bond
+    dimension above the Schmidt ranks, variational below (between the FCI
+    energy and the energy of the FCI vector compressed to the same M0)."""
+    ints, eri, psi0, ref = c1
+    print("case: DMRG Psi0 4 active orbitals M0=16", flush=True)
+    ctx = mp.Context(0)
+    ctx.load_integrals(4, 4, ints.h, ints.B)
+    ctx.load_h0_partition(ints.eps_virt)
+    g0 = inputs.psi0_guess(4, 4, 0, 16, 2000)
+    e = ctx.ground_state(4, 0, g0.bonds, g0.sites, 16)
+    assert e == pytest.approx(ref.E0, abs=1e-10)
+    g = inputs.psi1_guess(4, 4, 4, 0, 64, 1000)
+    ctx.load_psi1_guess(g.bonds, g.sites)
+    res = ctx.sweep(64)
+    assert res["e0"] == pytest.approx(ref.E0, abs=1e-10)
+    assert res["e2"] == pytest.approx(ref.E2, abs=1e-8)
+    print("case: DMRG Psi0 8 active orbitals M0=64", flush=True)
+    ints8 = inputs.integrals(8, 16, 32, 0)
+    eri8 = fock.eri_from_cholesky(ints8.B)
+    efci, c, ab = exact.active_ground_state(ints8.h, eri8, 8, 8, 0)
+    b0, s0 = exact.psi0_mps(c, ab, 8, 64)
+    v = exact.mps_to_vector(s0, 8)[fock.site_index(ab, 8)]
+    esvd = v @ (fock.hamiltonian(ints8.h[:8, :8], eri8[:8, :8, :8, :8], ab) @ v) / (v @ v)
+    ctx8 = mp.Context(0)
+    ctx8.load_integrals(8, 16, ints8.h, ints8.B)
+    ctx8.load_h0_partition(ints8.eps_virt)
+    g0 = inputs.psi0_guess(8, 8, 0, 64, 2000)
+    e8 = ctx8.ground_state(8, 0, g0.bonds, g0.sites, 64)
+    assert efci - 1e-10 <= e8 <= esvd + 1e-8
+
+
 def test_errors_are_reported(mp, c1):
     ints, eri, psi0, ref = c1
     ctx = mp.Context(0)

@@ -211,6 +211,24 @@ def test_mps_full_bond_dimension_is_exact():
     assert sw.e3() == pytest.approx(r.E3, abs=1e-9)
 
 
+def test_local_values_are_minima_and_guess_scale_free():
+    """At the local minimiser x of Eq. hyll, A x = -b, so the local value is
+    -x.A x <= 0; the result may not depend on the scale of the starting MPS
+    (an unnormalised random start must not stall CG on a drifted residual)."""
+    ints, eri = c1()
+    _, c, ab = exact.active_ground_state(ints.h, eri, 4, 4, 0)
+    psi0 = exact.psi0_mps(c, ab, 4)
+    g = inputs.psi1_guess(4, 4, 4, 0, 16, 1000)
+    runs = []
+    for scale in (1.0, 1e12):
+        sites = [s * (scale if i == 0 else 1.0) for i, s in enumerate(g.sites)]
+        sw = mps.Sweeper(ints.h, eri, 4, ints.eps_virt, 4, 0, psi0, (g.bonds, sites), 16)
+        sw.run()
+        assert all(t["e2"] <= 1e-15 for t in sw.trace)
+        runs.append(np.array([t["e2"] for t in sw.trace]))
+    np.testing.assert_allclose(runs[0], runs[1], rtol=0, atol=1e-12)
+
+
 def test_mps_upper_bound_and_monotone_in_m():
     """Hylleraas upper bound at every finite M1, non-increasing in M1."""
     prev = None
