@@ -120,6 +120,8 @@ typedef struct {
     double sigma_bytes;     /* algorithmic bytes (environments, vectors) of those applications */
     double t_total_s;       /* wall time of the sweeps (host clock, device synchronised) */
     int32_t flags;          /* bit 0: some local CG hit cg_max_iter (value still an upper bound) */
+    double t_phase[6];      /* host seconds: two-site operators, work-list builds, local solves
+                               (with device waits), truncation, environment updates, next guess */
 } mpspt_result;
 
 /* Run the sweep.  Errors: MPSPT_E_STATE if integrals, partition, Psi0 or the

@@ -119,6 +119,7 @@ void mpspt_destroy(mpspt_ctx* ctx) {
     if (!ctx) return;
     try {
         delete ctx;
+        mpspt::dev::trim();  // cached device blocks go back to the runtime
     } catch (...) {
     }
 }
@@ -224,6 +225,7 @@ mpspt_status mpspt_sweep(mpspt_ctx* ctx, const mpspt_sweep_params* params, mpspt
         out->sigma_bytes = r.bytes;
         out->t_total_s = r.t_total;
         out->flags = r.flags;
+        for (int k = 0; k < 6; ++k) out->t_phase[k] = r.t_phase[k];
     });
 }
 

@@ -74,8 +74,9 @@ struct Error {
 
 void set_device(int device, void* stream);  // throws Error
 int device_count();
-void* alloc(size_t bytes);                  // throws Error (MPSPT_E_NOMEM)
-void release(void* p);
+void* alloc(size_t bytes);                  // throws Error (MPSPT_E_NOMEM); stream-ordered pool
+void release(void* p);                      // back to the pool; safe while earlier launches run
+void trim();                                // return cached blocks to the runtime
 void h2d(void* dst, const void* src, size_t bytes);
 void d2h(void* dst, const void* src, size_t bytes);  // synchronous
 void d2d(void* dst, const void* src, size_t bytes);
@@ -98,7 +99,12 @@ struct KernelStats {
 void profile_enable(bool on);          // resets the counters
 KernelStats profile_stats(int kind);   // waits for outstanding launches
 void diag_grouped(const DiagGroup* groups, int ngroups, const DiagTerm* terms);
-void eig_batched(const EigJob* jobs, int njobs);
+// nmax: largest n among the jobs.  The kernel variant follows eig_class(nmax):
+// 0 = packed matrix and eigenvectors in LDS, 1 = packed matrix in LDS and
+// eigenvectors in global memory, 2 = everything in global memory; batch jobs
+// of one class together.
+void eig_batched(const EigJob* jobs, int njobs, int nmax);
+int eig_class(int n);
 
 // Vector kernels over length-n double vectors.  `scal` is a small device
 // array of scalars (layout in kernels.hip); all reductions are fixed-order.

@@ -22,14 +22,40 @@ namespace mpspt {
 namespace {
 dev::Error err(int code, const std::string& m) { return dev::Error{code, m}; }
 constexpr int kTile = 32;
+
+// Output blocks of an environment update keyed by (channel, bra sector) and
+// visited in ascending key order.
+template <class Tm>
+class OutTable {
+  public:
+    OutTable(int nch, int nbra) : nbra_(nbra), ik_((size_t)nch * nbra, -1), terms_((size_t)nch * nbra) {}
+    void add(int w, int ib, int ik, const Tm& t) {
+        const size_t s = (size_t)w * nbra_ + ib;
+        if (ik_[s] < 0) {
+            ik_[s] = ik;
+            used_.push_back(s);
+        } else if (ik_[s] != ik) {
+            throw err(MPSPT_E_QN, "inconsistent channel quantum numbers");
+        }
+        terms_[s].push_back(t);
+    }
+    template <class F>
+    void each(F&& f) {
+        std::sort(used_.begin(), used_.end());
+        for (size_t s : used_) f((int)(s / nbra_), (int)(s % nbra_), ik_[s], terms_[s]);
+    }
+
+  private:
+    size_t nbra_;
+    std::vector<int> ik_;
+    std::vector<std::vector<Tm>> terms_;
+    std::vector<size_t> used_;
+};
 }  // namespace
 
 // ------------------------------------------------------------- storage
 void DevBuf::reset() {
-    if (p) {
-        dev::sync();
-        dev::release(p);
-    }
+    if (p) dev::release(p);  // stream-ordered pool: no wait needed
     p = nullptr;
     n = 0;
 }
@@ -115,10 +141,16 @@ Two make_two(const Bond& L, const Bond& R, const std::set<QN>* mid_ok) {
 void Env::index() {
     idx.assign((size_t)nch * bra.q.size(), -1);
     by_w.assign(nch, {});
+    by_ib.assign(bra.q.size(), {});
     for (size_t b = 0; b < blk.size(); ++b) {
         idx[(size_t)blk[b].w * bra.q.size() + blk[b].ib] = (int)b;
         by_w[blk[b].w].push_back((int)b);
     }
+    for (int w = 0; w < nch; ++w)
+        for (size_t ib = 0; ib < bra.q.size(); ++ib) {
+            int b = idx[(size_t)w * bra.q.size() + ib];
+            if (b >= 0) by_ib[ib].push_back(b);
+        }
 }
 
 TwoOp make_twoop(const MPO& m, int i) {
@@ -234,6 +266,15 @@ void Engine::set_partition(std::vector<double> eps) {
 void Engine::build_mpos() {
     mpo_h0_ = build_mpo(OpKind::H0, k_a_, k_v_, h_, eri_, eps_);
     mpo_v_ = build_mpo(OpKind::VPsi0, k_a_, k_v_, h_, eri_, eps_);
+    twoop_cache_[0].clear();
+    twoop_cache_[1].clear();
+}
+
+const TwoOp& Engine::twoop(int which, int i) {
+    auto& cache = twoop_cache_[which];
+    if ((int)cache.size() < n_ - 1) cache.resize(n_ - 1);
+    if (!cache[i]) cache[i] = std::make_unique<TwoOp>(make_twoop(which == 0 ? mpo_h0_ : mpo_v_, i));
+    return *cache[i];
 }
 
 void Engine::load_site(Site& s, const std::vector<double>& dense) {
@@ -259,6 +300,7 @@ void Engine::load_site(Site& s, const std::vector<double>& dense) {
         if (!covered[i] && dense[i] != 0.0) throw err(MPSPT_E_QN, "site tensor entry outside the blocks its labels allow");
     }
     if (s.size) dev::h2d(s.data.p, host.data(), s.size * sizeof(double));
+    dev::sync();  // the staging vector is released on return
 }
 
 Env Engine::trivial_env(const Bond& bra, const Bond& ket) const {
@@ -273,6 +315,7 @@ Env Engine::trivial_env(const Bond& bra, const Bond& ket) const {
     e.data.alloc(1);
     double one = 1.0;
     dev::h2d(e.data.p, &one, sizeof(double));
+    dev::sync();
     return e;
 }
 
@@ -428,7 +471,7 @@ void Engine::env_left(Env& out, const Env& L, const Site& Abra, const Site& Aket
     }
     // stage b: contributions per output block (channel, bra sector)
     struct Tm { const double* A; int lda; const double* B; int ldb; int k; double a; };
-    std::map<std::pair<int, int>, std::pair<int, std::vector<Tm>>> outs;
+    OutTable<Tm> outs(out.nch, (int)out.bra.q.size());
     for (const MPOEntry& e : m.W[i]) {
         for (int s = 0; s < 4; ++s)
             for (int t = 0; t < 4; ++t) {
@@ -440,32 +483,27 @@ void Engine::env_left(Env& out, const Env& L, const Site& Abra, const Site& Aket
                     int ab = Abra.idx[B.ib * 4 + s];
                     int ak = Aket.idx[B.ik * 4 + t];
                     if (ab < 0 || ak < 0) continue;
-                    int ibp = Abra.blk[ab].jr, ikp = Aket.blk[ak].jr;
-                    auto& o = outs[{e.cout, ibp}];
-                    if (o.second.empty()) o.first = ikp;
-                    else if (o.first != ikp) throw err(MPSPT_E_QN, "inconsistent channel quantum numbers");
-                    o.second.push_back({Abra.at(ab), Abra.ld(ab), T_.p + toff[lb] + Aket.blk[ak].col,
-                                        Aket.pw[B.ik], B.rows, v});
+                    outs.add(e.cout, Abra.blk[ab].jr, Aket.blk[ak].jr,
+                             {Abra.at(ab), Abra.ld(ab), T_.p + toff[lb] + Aket.blk[ak].col, Aket.pw[B.ik], B.rows, v});
                 }
             }
     }
     size_t off = 0;
-    for (auto& kv : outs) {
-        int w = kv.first.first, ib = kv.first.second, ik = kv.second.first;
+    outs.each([&](int w, int ib, int ik, const std::vector<Tm>&) {
         out.blk.push_back({w, ib, ik, out.bra.d[ib], out.ket.d[ik], off});
         off += (size_t)out.bra.d[ib] * out.ket.d[ik];
-    }
+    });
     out.size = off;
     out.dq = m.dq[i + 1];
     out.index();
     out.data.alloc(std::max<size_t>(off, 1));
     GemmBatch gb;
     size_t bi = 0;
-    for (auto& kv : outs) {
+    outs.each([&](int, int, int, const std::vector<Tm>& terms) {
         const auto& B = out.blk[bi++];
         gb.group(out.data.p + B.off, B.cols, B.rows, B.cols, false);
-        for (const Tm& t : kv.second.second) gb.term(t.A, t.lda, true, t.B, t.ldb, false, t.k, t.a);
-    }
+        for (const Tm& t : terms) gb.term(t.A, t.lda, true, t.B, t.ldb, false, t.k, t.a);
+    });
     ga.upload();
     gb.upload();
     ga.run();
@@ -478,11 +516,13 @@ void Engine::env_right(Env& out, const Env& R, const Site& Abra, const Site& Ake
     out.bra = Abra.L;
     out.ket = Aket.L;
     struct Tm { const double* A; int lda; size_t toff; int ldb; int k; double a; };
-    std::unordered_map<uint64_t, size_t> tmap;  // (R block, Aket block) -> offset in T
+    // T(rb, t) = R block rb . (Aket block with right sector ib_ket(rb) and local state t)^T;
+    // for a fixed R block and local state that Aket block is unique
+    std::vector<size_t> toff(R.blk.size() * 4, (size_t)-1);
     struct Ta { int rb, ak; size_t off; };
     std::vector<Ta> tlist;
     size_t tsz = 0;
-    std::map<std::pair<int, int>, std::pair<int, std::vector<Tm>>> outs;
+    OutTable<Tm> outs(out.nch, (int)out.bra.q.size());
     for (const MPOEntry& e : m.W[i]) {
         for (int s = 0; s < 4; ++s)
             for (int t = 0; t < 4; ++t) {
@@ -494,22 +534,14 @@ void Engine::env_right(Env& out, const Env& R, const Site& Abra, const Site& Ake
                         if (Abra.blk[ab].s != s) continue;
                         for (int ak : Aket.by_jr[B.ik]) {
                             if (Aket.blk[ak].s != t) continue;
-                            uint64_t key = (uint64_t)rb << 32 | (uint32_t)ak;
-                            auto it = tmap.find(key);
-                            size_t to;
-                            if (it == tmap.end()) {
+                            size_t& to = toff[(size_t)rb * 4 + t];
+                            if (to == (size_t)-1) {
                                 to = tsz;
-                                tmap.emplace(key, to);
                                 tlist.push_back({rb, ak, to});
                                 tsz += (size_t)B.rows * Aket.blk[ak].rows;
-                            } else {
-                                to = it->second;
                             }
-                            int ibp = Abra.blk[ab].il, ikp = Aket.blk[ak].il;
-                            auto& o = outs[{e.cin, ibp}];
-                            if (o.second.empty()) o.first = ikp;
-                            else if (o.first != ikp) throw err(MPSPT_E_QN, "inconsistent channel quantum numbers");
-                            o.second.push_back({Abra.at(ab), Abra.ld(ab), to, Aket.blk[ak].rows, B.rows, v});
+                            outs.add(e.cin, Abra.blk[ab].il, Aket.blk[ak].il,
+                                     {Abra.at(ab), Abra.ld(ab), to, Aket.blk[ak].rows, B.rows, v});
                         }
                     }
                 }
@@ -524,22 +556,21 @@ void Engine::env_right(Env& out, const Env& R, const Site& Abra, const Site& Ake
         ga.term(R.data.p + B.off, B.cols, false, Aket.at(t.ak), Aket.ld(t.ak), true, B.cols, 1.0);
     }
     size_t off = 0;
-    for (auto& kv : outs) {
-        int w = kv.first.first, ib = kv.first.second, ik = kv.second.first;
+    outs.each([&](int w, int ib, int ik, const std::vector<Tm>&) {
         out.blk.push_back({w, ib, ik, out.bra.d[ib], out.ket.d[ik], off});
         off += (size_t)out.bra.d[ib] * out.ket.d[ik];
-    }
+    });
     out.size = off;
     out.dq = m.dq[i];
     out.index();
     out.data.alloc(std::max<size_t>(off, 1));
     GemmBatch gb;
     size_t bi = 0;
-    for (auto& kv : outs) {
+    outs.each([&](int, int, int, const std::vector<Tm>& terms) {
         const auto& B = out.blk[bi++];
         gb.group(out.data.p + B.off, B.cols, B.rows, B.cols, false);
-        for (const Tm& t : kv.second.second) gb.term(t.A, t.lda, false, T_.p + t.toff, t.ldb, false, t.k, t.a);
-    }
+        for (const Tm& t : terms) gb.term(t.A, t.lda, false, T_.p + t.toff, t.ldb, false, t.k, t.a);
+    });
     ga.upload();
     gb.upload();
     ga.run();
@@ -569,19 +600,17 @@ void Engine::build_effop(EffOp& op, const Env& L, const Env& R, const TwoOp& O, 
     size_t vsz = 0;
     for (size_t bb = 0; bb < bra.blk.size(); ++bb) {
         const auto& Y = bra.blk[bb];
-        for (int wp = 0; wp < R.nch; ++wp) {
-            int rb = R.find(wp, Y.jr);
-            if (rb < 0) continue;
+        for (int rb : R.by_ib[Y.jr]) {
+            const int wp = R.blk[rb].w;
             const auto& terms = O.by_out[(size_t)wp * 16 + Y.s1 * 4 + Y.s2];
             if (terms.empty()) continue;
             int jrk = R.blk[rb].ik;
             VB v{(int)bb, rb, 0, Y.rows, R.blk[rb].cols, {}};
             for (const auto& t : terms) {
-                QN qk = bra.L.q[Y.il] - L.dq[t.w];
-                int ik = ket.L.find(qk);
-                if (ik < 0) continue;
-                int lb = L.find(t.w, Y.il);
-                if (lb < 0 || L.blk[lb].ik != ik || uoff[lb] == (size_t)-1) continue;
+                // the L block of channel w at this bra sector fixes the ket sector
+                const int lb = L.find(t.w, Y.il);
+                if (lb < 0 || uoff[lb] == (size_t)-1) continue;
+                const int ik = L.blk[lb].ik;
                 int xb = ket.idx[(ik * 4 + t.s1) * 4 + t.s2];
                 if (xb < 0 || ket.blk[xb].jr != jrk) continue;
                 v.t.push_back({uoff[lb] + ket.blk[xb].col, ket.pw[ik], t.v});
@@ -632,9 +661,9 @@ void Engine::build_diag(const Env& L, const Env& R, const TwoOp& O, const Two& l
     for (size_t bb = 0; bb < lay.blk.size(); ++bb) {
         const auto& Y = lay.blk[bb];
         dev::DiagGroup g{d + lay.off((int)bb), lay.ld((int)bb), Y.rows, Y.cols, (int)ts.size(), 0, shift};
-        for (int wp = 0; wp < R.nch; ++wp) {
-            int rb = R.find(wp, Y.jr);
-            if (rb < 0 || R.blk[rb].ik != Y.jr) continue;
+        for (int rb : R.by_ib[Y.jr]) {
+            const int wp = R.blk[rb].w;
+            if (R.blk[rb].ik != Y.jr) continue;
             for (const auto& t : O.by_out[(size_t)wp * 16 + Y.s1 * 4 + Y.s2]) {
                 if (t.s1 != Y.s1 || t.s2 != Y.s2) continue;
                 int lb = L.find(t.w, Y.il);
@@ -765,12 +794,20 @@ double Engine::truncate(int i, bool forward, const Two& lay, const double* x, in
     }
     gr.upload();
     gr.run();
-    std::vector<dev::EigJob> jobs;
-    for (int q = 0; q < ng; ++q)
-        if (gdim[q] > 0) jobs.push_back({rho_.p + goff[q], eigV_.p + goff[q], eigw_.p + woff[q], gdim[q], 0});
-    DevArr<dev::EigJob> dj;
-    dj.upload(jobs);
-    if (!jobs.empty()) dev::eig_batched(dj.p, (int)jobs.size());
+    // one eigensolver launch per kernel variant (by how much of the problem fits in LDS)
+    std::vector<dev::EigJob> jobs[3];
+    int nmax[3] = {0, 0, 0};
+    for (int q = 0; q < ng; ++q) {
+        if (gdim[q] <= 0) continue;
+        const int c = dev::eig_class(gdim[q]);
+        jobs[c].push_back({rho_.p + goff[q], eigV_.p + goff[q], eigw_.p + woff[q], gdim[q], 0});
+        nmax[c] = std::max(nmax[c], gdim[q]);
+    }
+    DevArr<dev::EigJob> dj[3];
+    for (int c = 0; c < 3; ++c) {
+        dj[c].upload(jobs[c]);
+        if (!jobs[c].empty()) dev::eig_batched(dj[c].p, (int)jobs[c].size(), nmax[c]);
+    }
     std::vector<double> wall(std::max<size_t>(wsz, 1));
     dev::d2h(wall.data(), eigw_.p, wsz * sizeof(double));
     std::vector<std::vector<double>> w(ng);
@@ -866,14 +903,24 @@ int Engine::solve(int i, double& e2) {
     for (DevBuf* b : {&x_, &b_, &d_, &r_, &z_, &p_, &q_}) b->ensure(std::max<size_t>(n, 1));
     partials_.ensure(dev::kPartials);
     scal_.ensure(dev::S_N);
-    TwoOp O = make_twoop(mpo_h0_, i);
-    TwoOp Ov = make_twoop(mpo_v_, i);
+    double t = dev::now();
+    const TwoOp& O = twoop(0, i);
+    const TwoOp& Ov = twoop(1, i);
+    res_.t_phase[0] += dev::now() - t;
+    t = dev::now();
     EffOp rhs;
     build_effop(rhs, LV_[i], RV_[i + 2], Ov, P0x_lay_[i], P0x_[i].p, lay, b_.p);
     rhs.run();
     build_diag(LH_[i], RH_[i + 2], O, lay, d_.p, -E0_);
     EffOp sig;
     build_effop(sig, LH_[i], RH_[i + 2], O, lay, p_.p, lay, q_.p);
+    res_.t_phase[1] += dev::now() - t;
+    t = dev::now();
+    struct PhaseTimer {
+        double t0;
+        double& acc;
+        ~PhaseTimer() { acc += dev::now() - t0; }
+    } cg_timer{t, res_.t_phase[2]};
     auto apply = [&]() {
         sig.run();
         dev::cg_shift_dot(q_.p, p_.p, E0_, n, scal_.p, partials_.p);
@@ -1027,11 +1074,17 @@ double Engine::run_sweeps(int M, int n_sweeps, int max_sweeps, double e_tol) {
                 res_.cg_iters += it;
                 last_lay_ = xlay_;
                 Site C;
+                double t = dev::now();
                 double disc = truncate(i, fwd, xlay_, x_.p, M, C);
+                res_.t_phase[3] += dev::now() - t;
+                t = dev::now();
                 if (fwd) upd_left(i);
                 else upd_right(i + 1);
+                res_.t_phase[4] += dev::now() - t;
+                t = dev::now();
                 next_guess(i, fwd, C);
                 dev::sync();
+                res_.t_phase[5] += dev::now() - t;
                 trace_.push_back({e2, disc, dev::now() - t0_, it});
                 maxd = std::max(maxd, disc);
                 res_.n_steps++;
@@ -1099,6 +1152,7 @@ double Engine::ground_state(int n_elec, int two_sz, const std::vector<Bond>& bon
     gs_ = true;
     n_ = k_a_;
     mpo_h0_ = build_mpo(OpKind::HAct, k_a_, k_v_, h_, eri_, eps_);
+    twoop_cache_[0].clear();
     adm_ = adm;
     res_ = SweepResult();
     trace_.clear();
@@ -1122,6 +1176,7 @@ double Engine::ground_state(int n_elec, int two_sz, const std::vector<Bond>& bon
         gs_ = false;
         n_ = n_save;
         mpo_h0_ = std::move(h0_save);
+        twoop_cache_[0].clear();
         adm_ = std::move(adm_save);
         A_.clear();
         throw;
@@ -1129,6 +1184,7 @@ double Engine::ground_state(int n_elec, int two_sz, const std::vector<Bond>& bon
     gs_ = false;
     n_ = n_save;
     mpo_h0_ = std::move(h0_save);
+    twoop_cache_[0].clear();
     adm_ = std::move(adm_save);
     A_.clear();
     gs_trace_ = trace_;
@@ -1147,7 +1203,7 @@ int Engine::davidson(int i, double& e) {
     dav_AV_.ensure(std::max<size_t>(n, 1) * kMax);
     partials_.ensure(dev::kPartials);
     scal_.ensure(dev::S_N);
-    TwoOp O = make_twoop(mpo_h0_, i);
+    const TwoOp& O = twoop(0, i);
     build_diag(LH_[i], RH_[i + 2], O, lay, d_.p, 0.0);
     EffOp sig;
     build_effop(sig, LH_[i], RH_[i + 2], O, lay, p_.p, lay, q_.p);

@@ -39,10 +39,7 @@ class DevArr {
     DevArr(const DevArr&) = delete;
     DevArr& operator=(const DevArr&) = delete;
     ~DevArr() {
-        if (p) {
-            dev::sync();
-            dev::release(p);
-        }
+        if (p) dev::release(p);  // stream-ordered pool
     }
     void upload(const std::vector<T>& v) {
         if (v.size() > cap) {
@@ -104,6 +101,7 @@ struct Env {
     std::vector<Blk> blk;
     std::vector<int> idx;      // w * nbra + ib -> block or -1
     std::vector<std::vector<int>> by_w;
+    std::vector<std::vector<int>> by_ib;  // blocks per bra sector, ascending channel
     std::vector<QN> dq;        // per channel
     size_t size = 0;
     DevBuf data;
@@ -185,6 +183,10 @@ struct SweepResult {
     int n_sweeps = 0, n_steps = 0, flags = 0;
     long long cg_iters = 0, sigma_calls = 0;
     std::vector<double> e2_sweep;
+    // host wall time per phase: two-site operators, work-list builds, local
+    // solves (including waits on the device), truncation, environment updates,
+    // next guess
+    double t_phase[6] = {0, 0, 0, 0, 0, 0};
 };
 
 class Engine {
@@ -240,6 +242,9 @@ class Engine {
     std::vector<StepRecord> gs_trace_;
 
     void build_mpos();
+    // two-site operators per window, built once per MPO (which = 0: H0, 1: V)
+    std::vector<std::unique_ptr<TwoOp>> twoop_cache_[2];
+    const TwoOp& twoop(int which, int i);
     Env trivial_env(const Bond& bra, const Bond& ket) const;
     void env_left(Env& out, const Env& L, const Site& Abra, const Site& Aket, const MPO& m, int i);
     void env_right(Env& out, const Env& R, const Site& Abra, const Site& Aket, const MPO& m, int i);

@@ -13,7 +13,9 @@
 
 #include <chrono>
 #include <cmath>
+#include <algorithm>
 #include <cstdio>
+#include <unordered_map>
 #include <vector>
 
 #include "../../include/mpspt.h"
@@ -24,6 +26,8 @@ namespace dev {
 
 namespace {
 hipStream_t g_stream = nullptr;
+int g_eig_lds_max = 0;
+size_t g_lds_budget = 0;
 
 void check(hipError_t e, const char* what) {
     if (e != hipSuccess) {
@@ -249,6 +253,140 @@ __global__ __launch_bounds__(256) void k_eig_jacobi(const EigJob* __restrict__ j
     for (int i = tid; i < n; i += blockDim.x) J.w[i] = V[i];
 }
 
+__device__ double block_sum_1024(double v, double* red16) {
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (lane == 0) red16[wave] = v;
+    __syncthreads();
+    double s = 0.0;
+    for (int w = 0; w < 16; ++w) s += red16[w];
+    __syncthreads();
+    return s;
+}
+
+// Round-robin Jacobi on the packed upper triangle held in LDS.  The disjoint
+// rotations of one round act on the matrix as J^T A J with J block diagonal in
+// the pair basis, so every 2x2 block formed by two pairs (k1 <= k2) is
+// updated independently: B' = G(k1) B G(k2)^T, with the diagonal blocks set
+// by the closed Jacobi form (a_pq' = 0).  One barrier per round.  The
+// transposed eigenvector matrix lives in LDS (VT_LDS) or in the job's V
+// workspace.
+__device__ __forceinline__ int tri_off(int i, int n) { return i * n - (i * (i - 1)) / 2; }
+__device__ __forceinline__ int tri_idx(int i, int j, int n) {  // i <= j
+    return tri_off(i, n) + (j - i);
+}
+
+template <bool VT_LDS>
+__global__ __launch_bounds__(1024) void k_eig_jacobi_packed(const EigJob* __restrict__ jobs) {
+    extern __shared__ double lds[];
+    const EigJob J = jobs[blockIdx.x];
+    const int n = J.n;
+    const int tid = threadIdx.x;
+    double* P = lds;                                           // n (n + 1) / 2
+    double* Vt = VT_LDS ? lds + (n * (n + 1)) / 2 : J.V;       // n x n, row p = eigenvector p
+    __shared__ double red16[16];
+    __shared__ double cs[128], sn[128];
+    __shared__ int pp[128], qq[128];
+    for (int e = tid; e < n * n; e += 1024) {
+        const int i = e / n, j = e - i * n;
+        if (i <= j) P[tri_idx(i, j, n)] = J.A[e];
+        Vt[e] = (i == j) ? 1.0 : 0.0;
+    }
+    __syncthreads();
+    const int m = n + (n & 1);
+    const int npair = m / 2;
+    for (int sweep = 0; sweep < 60 && n > 1; ++sweep) {
+        double off = 0.0, tot = 0.0;
+        for (int e = tid; e < n * n; e += 1024) {
+            const int i = e / n, j = e - i * n;
+            if (i > j) continue;
+            const double a = P[tri_idx(i, j, n)];
+            tot += (i == j) ? a * a : 2.0 * a * a;
+            if (i != j) off += 2.0 * a * a;
+        }
+        off = block_sum_1024(off, red16);
+        tot = block_sum_1024(tot, red16);
+        if (off <= 1e-30 * tot || tot == 0.0) break;
+        for (int round = 0; round < m - 1; ++round) {
+            if (tid < npair) {
+                const int k = tid;
+                int p = (round + k) % (m - 1);
+                int q = (k == 0) ? (m - 1) : (round - k + m - 1) % (m - 1);
+                if (p > q) { int t = p; p = q; q = t; }
+                double c = 1.0, s = 0.0;
+                if (q < n) {
+                    const double apq = P[tri_idx(p, q, n)];
+                    if (apq != 0.0) {
+                        const double app = P[tri_idx(p, p, n)], aqq = P[tri_idx(q, q, n)];
+                        const double tau = (aqq - app) / (2.0 * apq);
+                        const double tt = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+                        c = 1.0 / sqrt(1.0 + tt * tt);
+                        s = tt * c;
+                    }
+                }
+                pp[k] = p; qq[k] = q; cs[k] = c; sn[k] = s;
+            }
+            __syncthreads();
+            // 2x2 blocks of pair-of-pairs, k1 <= k2
+            for (int b = tid; b < npair * npair; b += 1024) {
+                const int k1 = b / npair, k2 = b - k1 * npair;
+                if (k1 > k2) continue;
+                const double s1 = sn[k1], s2 = sn[k2];
+                if (s1 == 0.0 && s2 == 0.0) continue;
+                const int p1 = pp[k1], q1 = qq[k1], p2 = pp[k2], q2 = qq[k2];
+                const double c1 = cs[k1], c2 = cs[k2];
+                if (k1 == k2) {
+                    if (q1 >= n) continue;
+                    const double apq = P[tri_idx(p1, q1, n)];
+                    const double t = s1 / c1;
+                    P[tri_idx(p1, p1, n)] -= t * apq;
+                    P[tri_idx(q1, q1, n)] += t * apq;
+                    P[tri_idx(p1, q1, n)] = 0.0;
+                    continue;
+                }
+                // rows {p1, q1} (q1 may be the dummy index n), columns {p2, q2}
+                const bool r2 = q1 < n, c2ok = q2 < n;
+                auto at = [&](int i, int j) -> double& {
+                    return i <= j ? P[tri_idx(i, j, n)] : P[tri_idx(j, i, n)];
+                };
+                double b00 = at(p1, p2), b01 = c2ok ? at(p1, q2) : 0.0;
+                double b10 = r2 ? at(q1, p2) : 0.0, b11 = (r2 && c2ok) ? at(q1, q2) : 0.0;
+                // rows: G(k1) = [[c, -s], [s, c]]
+                double u00 = c1 * b00 - s1 * b10, u01 = c1 * b01 - s1 * b11;
+                double u10 = s1 * b00 + c1 * b10, u11 = s1 * b01 + c1 * b11;
+                // columns
+                double v00 = c2 * u00 - s2 * u01, v01 = s2 * u00 + c2 * u01;
+                double v10 = c2 * u10 - s2 * u11, v11 = s2 * u10 + c2 * u11;
+                at(p1, p2) = v00;
+                if (c2ok) at(p1, q2) = v01;
+                if (r2) at(q1, p2) = v10;
+                if (r2 && c2ok) at(q1, q2) = v11;
+            }
+            // eigenvector rows p, q of Vt
+            for (int e = tid; e < npair * n; e += 1024) {
+                const int k = e / n, j = e - k * n;
+                const int p = pp[k], q = qq[k];
+                if (q >= n || sn[k] == 0.0) continue;
+                const double c = cs[k], s = sn[k];
+                const double vp = Vt[p * n + j], vq = Vt[q * n + j];
+                Vt[p * n + j] = c * vp - s * vq;
+                Vt[q * n + j] = s * vp + c * vq;
+            }
+            __syncthreads();
+        }
+    }
+    for (int i = tid; i < n; i += 1024) {
+        const double di = P[tri_idx(i, i, n)];
+        int rank = 0;
+        for (int j = 0; j < n; ++j) {
+            const double dj = P[tri_idx(j, j, n)];
+            rank += (dj > di) || (dj == di && j < i);
+        }
+        J.w[rank] = di;
+        for (int r = 0; r < n; ++r) J.A[r * n + rank] = Vt[i * n + r];
+    }
+}
+
 // ---------------------------------------------------------------- vectors
 __device__ void block_partial(double v, double* red, double* out) {
     const int tid = threadIdx.x;
@@ -385,21 +523,82 @@ void set_device(int device, void* stream) {
     if (std::string(prop.gcnArchName).rfind("gfx950", 0) != 0)
         throw Error{MPSPT_E_NODEV, std::string("device is ") + prop.gcnArchName + ", the library is built for gfx950"};
     g_stream = static_cast<hipStream_t>(stream);
+    // dynamic LDS available to the eigensolver next to ~4 KB of static shared memory;
+    // the packed upper triangle (n (n + 1) / 2 doubles) must fit
+    int lds = 0;
+    check(hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, device), "hipDeviceGetAttribute");
+    const long budget = (long)lds - 4096;
+    g_lds_budget = budget > 0 ? (size_t)budget : 0;
+    int nmax = 0;
+    while ((long)(nmax + 1) * (nmax + 2) / 2 * 8 <= budget && nmax < 255) ++nmax;
+    if (budget > 65536 - 4096) {
+        check(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_eig_jacobi_packed<true>),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)budget),
+              "hipFuncSetAttribute");
+        check(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_eig_jacobi_packed<false>),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)budget),
+              "hipFuncSetAttribute");
+    }
+    g_eig_lds_max = nmax;
 }
 
+// Stream-ordered caching allocator.  All device work of the library is issued
+// on one stream, so a block released here can be handed to the next request
+// at once: any later use is ordered after every earlier use on that stream.
+// Sizes are rounded to 1/8 steps between powers of two; nothing is returned
+// to the runtime before trim().
+namespace {
+std::unordered_map<size_t, std::vector<void*>> g_free;
+std::unordered_map<void*, size_t> g_size;
+
+size_t size_class(size_t b) {
+    if (b <= 256) return 256;
+    size_t p = 1;
+    while (p < b) p <<= 1;
+    const size_t step = std::max<size_t>(p / 16, 256);
+    return (b + step - 1) / step * step;
+}
+}  // namespace
+
 void* alloc(size_t bytes) {
-    void* p = nullptr;
     if (bytes == 0) return nullptr;
-    check(hipMalloc(&p, bytes), "hipMalloc");
+    const size_t c = size_class(bytes);
+    auto it = g_free.find(c);
+    if (it != g_free.end() && !it->second.empty()) {
+        void* p = it->second.back();
+        it->second.pop_back();
+        return p;
+    }
+    void* p = nullptr;
+    hipError_t e = hipMalloc(&p, c);
+    if (e == hipErrorOutOfMemory) {  // give cached blocks back and retry once
+        (void)hipGetLastError();
+        trim();
+        e = hipMalloc(&p, c);
+    }
+    check(e, "hipMalloc");
+    g_size[p] = c;
     return p;
 }
 void release(void* p) {
-    if (p) (void)hipFree(p);
+    if (!p) return;
+    auto it = g_size.find(p);
+    if (it == g_size.end()) return;
+    g_free[it->second].push_back(p);
+}
+void trim() {
+    (void)hipStreamSynchronize(g_stream);
+    for (auto& kv : g_free)
+        for (void* p : kv.second) {
+            (void)hipFree(p);
+            g_size.erase(p);
+        }
+    g_free.clear();
 }
 void h2d(void* dst, const void* src, size_t bytes) {
     if (!bytes) return;
+    // ordered on the stream; pageable sources are staged by the runtime before it returns
     check(hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, g_stream), "hipMemcpyAsync H2D");
-    check(hipStreamSynchronize(g_stream), "hipStreamSynchronize");
 }
 void d2h(void* dst, const void* src, size_t bytes) {
     if (!bytes) return;
@@ -509,11 +708,28 @@ void diag_grouped(const DiagGroup* groups, int ngroups, const DiagTerm* terms) {
     hipLaunchKernelGGL(k_diag_grouped, dim3(ngroups), dim3(256), 0, g_stream, groups, terms);
     check(hipGetLastError(), "k_diag_grouped");
 }
-void eig_batched(const EigJob* jobs, int njobs) {
+void eig_batched(const EigJob* jobs, int njobs, int nmax) {
     if (njobs <= 0) return;
     Prof p(K_EIG, 0, 0);
-    hipLaunchKernelGGL(k_eig_jacobi, dim3(njobs), dim3(256), 0, g_stream, jobs);
-    check(hipGetLastError(), "k_eig_jacobi");
+    const size_t packed = (size_t)nmax * (nmax + 1) / 2 * sizeof(double);
+    const size_t vt = (size_t)nmax * nmax * sizeof(double);
+    if (packed + vt <= g_lds_budget) {
+        hipLaunchKernelGGL(k_eig_jacobi_packed<true>, dim3(njobs), dim3(1024), packed + vt, g_stream, jobs);
+        check(hipGetLastError(), "k_eig_jacobi_packed");
+    } else if (packed <= g_lds_budget) {
+        hipLaunchKernelGGL(k_eig_jacobi_packed<false>, dim3(njobs), dim3(1024), packed, g_stream, jobs);
+        check(hipGetLastError(), "k_eig_jacobi_packed");
+    } else {
+        hipLaunchKernelGGL(k_eig_jacobi, dim3(njobs), dim3(256), 0, g_stream, jobs);
+        check(hipGetLastError(), "k_eig_jacobi");
+    }
+}
+int eig_class(int n) {
+    const size_t packed = (size_t)n * (n + 1) / 2 * sizeof(double);
+    const size_t vt = (size_t)n * n * sizeof(double);
+    if (packed + vt <= g_lds_budget) return 0;
+    if (packed <= g_lds_budget) return 1;
+    return 2;
 }
 
 void dot(const double* a, const double* b, size_t n, double* scal, int slot, double* partials) {

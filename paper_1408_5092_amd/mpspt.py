@@ -42,7 +42,7 @@ class Result(C.Structure):
                 ("e2_sweep", C.c_double * 64), ("max_discarded", C.c_double),
                 ("cg_iters", C.c_int64), ("sigma_calls", C.c_int64),
                 ("sigma_flops", C.c_double), ("sigma_bytes", C.c_double),
-                ("t_total_s", C.c_double), ("flags", C.c_int32)]
+                ("t_total_s", C.c_double), ("flags", C.c_int32), ("t_phase", C.c_double * 6)]
 
 
 _lib = None
@@ -184,6 +184,7 @@ class Context:
         self._ok(self.lib.mpspt_sweep(self.h, C.byref(p), C.byref(r)))
         out = {f: getattr(r, f) for f, _ in Result._fields_}
         out["e2_sweep"] = list(r.e2_sweep)[:r.n_sweeps_done]
+        out["t_phase"] = dict(zip(("twoop", "build", "solve", "truncate", "env", "guess"), list(r.t_phase)))
         return out
 
     def profile(self, enable=True):
