@@ -131,7 +131,9 @@ mpspt_status mpspt_sweep(mpspt_ctx *ctx, const mpspt_sweep_params *params, mpspt
 /* Kernel timing: enable = 1 starts recording HIP events around every launch
  * on the context's stream (counters reset), 0 stops.  mpspt_kernel_stats
  * returns, for kind 0 = grouped GEMM (k_gemm_grouped), 1 = grouped block
- * axpy, 2 = Jacobi eigensolver, 3 = Jacobi diagonal, the summed event time,
+ * axpy, 2 = tridiagonal reduction and eigenvalues (k_eig_reduce), 3 = Jacobi
+ * diagonal, 4 = kept-subspace bases (k_eig_vectors), 5 = CG / Davidson
+ * vector kernels, the summed event time,
  * launch count and the algorithmic flops / bytes of those launches (flops
  * 2mnk per block product; bytes: every operand block read once and every
  * output block written once).  Waits for outstanding launches. */

@@ -57,14 +57,17 @@ struct DiagGroup {
     double shift;
 };
 
-// Symmetric eigenproblem: A (n x n, row major) is replaced by its
-// eigenvectors (columns, eigenvalues descending), w receives eigenvalues;
-// V is n x n workspace.
+// Symmetric eigenproblem of a density-matrix sector.  eig_reduce: A (n x n,
+// row major, symmetric) is reduced to tridiagonal form (reflectors in V, n x n;
+// tridiagonal in t) and w receives all eigenvalues, descending.  eig_vectors:
+// the first k columns of A receive an orthonormal basis of the invariant
+// subspace of the k largest eigenvalues.  t holds eig_work(n) doubles.
 struct EigJob {
     double* A;
     double* V;
     double* w;
-    int32_t n, pad;
+    double* t;
+    int32_t n, k;
 };
 
 struct Error {
@@ -91,7 +94,7 @@ void axpy_grouped(const AxpyGroup* groups, int ngroups, const AxpyTerm* terms, d
                   double bytes = 0);
 
 // Per-kernel timing with HIP events recorded on the library's stream.
-enum KernelKind { K_GEMM = 0, K_AXPY = 1, K_EIG = 2, K_DIAG = 3, K_VEC = 4, K_COUNT = 5 };
+enum KernelKind { K_GEMM = 0, K_AXPY = 1, K_EIG = 2, K_DIAG = 3, K_EIGV = 4, K_VEC = 5, K_COUNT = 6 };
 struct KernelStats {
     double seconds = 0, flops = 0, bytes = 0;
     long long launches = 0;
@@ -99,12 +102,15 @@ struct KernelStats {
 void profile_enable(bool on);          // resets the counters
 KernelStats profile_stats(int kind);   // waits for outstanding launches
 void diag_grouped(const DiagGroup* groups, int ngroups, const DiagTerm* terms);
-// nmax: largest n among the jobs.  The kernel variant follows eig_class(nmax):
-// 0 = packed matrix and eigenvectors in LDS, 1 = packed matrix in LDS and
-// eigenvectors in global memory, 2 = everything in global memory; batch jobs
-// of one class together.
-void eig_batched(const EigJob* jobs, int njobs, int nmax);
-int eig_class(int n);
+// nmax / kmax: largest n / k among the jobs.  Variant 0 of each kernel keeps
+// the matrix (eig_reduce) or the basis (eig_vectors) in LDS, variant 1 in
+// global memory; batch jobs of one class together.  eig_vectors adds one to
+// *status (device int) per job whose basis could not be orthonormalised.
+void eig_reduce(const EigJob* jobs, int njobs, int nmax);
+void eig_vectors(const EigJob* jobs, int njobs, int nmax, int kmax, int* status);
+int eig_reduce_class(int n);
+int eig_vectors_class(int n, int k);
+size_t eig_work(int n);
 
 // Vector kernels over length-n double vectors.  `scal` is a small device
 // array of scalars (layout in kernels.hip); all reductions are fixed-order.

@@ -794,25 +794,64 @@ double Engine::truncate(int i, bool forward, const Two& lay, const double* x, in
     }
     gr.upload();
     gr.run();
-    // one eigensolver launch per kernel variant (by how much of the problem fits in LDS)
-    std::vector<dev::EigJob> jobs[3];
-    int nmax[3] = {0, 0, 0};
+    // tridiagonal reduction and all eigenvalues: one launch per kernel variant
+    // (by whether the matrix fits in LDS)
+    size_t tsz = 0;
+    std::vector<size_t> toff(ng);
     for (int q = 0; q < ng; ++q) {
-        if (gdim[q] <= 0) continue;
-        const int c = dev::eig_class(gdim[q]);
-        jobs[c].push_back({rho_.p + goff[q], eigV_.p + goff[q], eigw_.p + woff[q], gdim[q], 0});
-        nmax[c] = std::max(nmax[c], gdim[q]);
+        toff[q] = tsz;
+        tsz += dev::eig_work(gdim[q]);
     }
-    DevArr<dev::EigJob> dj[3];
-    for (int c = 0; c < 3; ++c) {
-        dj[c].upload(jobs[c]);
-        if (!jobs[c].empty()) dev::eig_batched(dj[c].p, (int)jobs[c].size(), nmax[c]);
+    eigT_.ensure(std::max<size_t>(tsz, 1));
+    std::vector<dev::EigJob> all(ng);
+    for (int q = 0; q < ng; ++q)
+        all[q] = {rho_.p + goff[q], eigV_.p + goff[q], eigw_.p + woff[q], eigT_.p + toff[q], gdim[q], 0};
+    {
+        std::vector<dev::EigJob> jobs[2];
+        int nmax[2] = {0, 0};
+        for (int q = 0; q < ng; ++q) {
+            if (gdim[q] <= 0) continue;
+            const int c = dev::eig_reduce_class(gdim[q]);
+            jobs[c].push_back(all[q]);
+            nmax[c] = std::max(nmax[c], gdim[q]);
+        }
+        DevArr<dev::EigJob> dj[2];
+        for (int c = 0; c < 2; ++c) {
+            dj[c].upload(jobs[c]);
+            if (!jobs[c].empty()) dev::eig_reduce(dj[c].p, (int)jobs[c].size(), nmax[c]);
+        }
     }
     std::vector<double> wall(std::max<size_t>(wsz, 1));
     dev::d2h(wall.data(), eigw_.p, wsz * sizeof(double));
     std::vector<std::vector<double>> w(ng);
     for (int q = 0; q < ng; ++q) w[q].assign(wall.begin() + woff[q], wall.begin() + woff[q] + gdim[q]);
     Sel sel = select_states(w, M);
+    // orthonormal bases of the kept subspaces (first kept[q] columns of each
+    // density matrix's buffer)
+    {
+        std::vector<dev::EigJob> jobs[2];
+        int nmax[2] = {0, 0}, kmax[2] = {0, 0};
+        for (int q = 0; q < ng; ++q) {
+            if (sel.kept[q] <= 0) continue;
+            dev::EigJob j = all[q];
+            j.k = sel.kept[q];
+            const int c = dev::eig_vectors_class(j.n, j.k);
+            jobs[c].push_back(j);
+            nmax[c] = std::max(nmax[c], j.n);
+            kmax[c] = std::max(kmax[c], j.k);
+        }
+        eigS_.ensure(1);
+        int* status = reinterpret_cast<int*>(eigS_.p);
+        dev::zero(status, sizeof(int));
+        DevArr<dev::EigJob> dj[2];
+        for (int c = 0; c < 2; ++c) {
+            dj[c].upload(jobs[c]);
+            if (!jobs[c].empty()) dev::eig_vectors(dj[c].p, (int)jobs[c].size(), nmax[c], kmax[c], status);
+        }
+        int bad = 0;
+        dev::d2h(&bad, status, sizeof(int));
+        if (bad) throw err(MPSPT_E_STATE, "eigensolver could not orthonormalise a kept basis");
+    }
     Bond nb;
     std::vector<int> gid;  // new sector -> group
     for (int q = 0; q < ng; ++q)
@@ -824,7 +863,7 @@ double Engine::truncate(int i, bool forward, const Two& lay, const double* x, in
     if (nb.q.empty()) throw err(MPSPT_E_STATE, "truncation kept no states (zero two-site tensor)");
     std::vector<std::vector<Part>*> gparts;
     for (auto& kv : groups) gparts.push_back(&kv.second);
-    const double* EV = rho_.p;  // eigenvectors replace the density matrices
+    const double* EV = rho_.p;  // kept bases replace the density matrices
     if (forward) {
         Site An = make_site(lay.L, nb);
         AxpyBatch cp;

@@ -226,7 +226,7 @@ class Engine {
     // environments
     std::vector<Env> LH_, RH_, LV_, RV_;
     // work buffers
-    DevBuf T_, rho_, eigV_, eigw_, partials_, scal_;
+    DevBuf T_, rho_, eigV_, eigw_, eigT_, eigS_, partials_, scal_;
     DevBuf x_, b_, d_, r_, z_, p_, q_, xg_;
     Two xlay_, last_lay_;
     double cg_tol2_ = 1e-20;

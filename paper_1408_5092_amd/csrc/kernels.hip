@@ -6,8 +6,8 @@
 //   block-sparse contraction is one launch and its result is deterministic.
 // * k_axpy_grouped: linear combinations of dense blocks (MPO coefficients).
 // * k_diag_grouped: Jacobi diagonal of the effective operator.
-// * k_eig_jacobi: cyclic two-sided Jacobi eigensolver, one workgroup per
-//   symmetric matrix, parallel rotations in round-robin order.
+// * k_eig_tridiag: batched symmetric eigensolver (Householder tridiagonal
+//   reduction, accumulated Q, implicit QL), one workgroup per matrix.
 // * CG vector kernels with fixed-order two-pass reductions.
 #include <hip/hip_runtime.h>
 
@@ -26,7 +26,6 @@ namespace dev {
 
 namespace {
 hipStream_t g_stream = nullptr;
-int g_eig_lds_max = 0;
 size_t g_lds_budget = 0;
 
 void check(hipError_t e, const char* what) {
@@ -144,246 +143,396 @@ __global__ __launch_bounds__(256) void k_diag_grouped(const DiagGroup* __restric
 }
 
 // ------------------------------------------------------------------ EIGEN
-__device__ double block_sum(double v, double* red) {
-    const int tid = threadIdx.x;
-    red[tid] = v;
-    __syncthreads();
-    for (int s = blockDim.x / 2; s > 0; s >>= 1) {
-        if (tid < s) red[tid] += red[tid + s];
-        __syncthreads();
-    }
-    double r = red[0];
-    __syncthreads();
-    return r;
+// Symmetric eigensolver for density matrices, in two launches with the
+// choice of the kept count on the host between them.  One 1024-thread
+// workgroup per matrix.
+//
+// k_eig_reduce: Householder reduction to tridiagonal form (lower variant),
+//   then every eigenvalue by multisection on Sturm counts: the eigenvalue of
+//   ascending index j is owned by a group of L lanes (L = 1024 / n rounded
+//   down to a power of two, at most 64) that evaluate L interior points of
+//   its bracket at once, so each step shrinks the bracket (L + 1)-fold.
+// k_eig_vectors: for the k largest eigenvalues, an orthonormal basis of
+//   their invariant subspace: inverse iteration on the tridiagonal matrix
+//   (one thread per vector, random start, three solves with partial
+//   pivoting), sequential orthogonalisation inside clusters closer than
+//   1000 ulps of the norm, two passes of Cholesky QR over all k vectors,
+//   then the Householder reflectors applied backwards.
+//
+// Job buffers: A (n x n, row major) holds the symmetric input and, after
+// k_eig_vectors, the basis in its first k columns; V (n x n) receives the
+// reflectors (row r: tau at V[r][r], v at V[r][r+2..], v[r+1] = 1); w (n)
+// the eigenvalues in descending order; t (eig_work(n) doubles) the
+// tridiagonal matrix and scratch.
+constexpr int EIG_MAXN = 512;
+constexpr double EIG_EPS = 2.220446049250313e-16;
+
+__device__ __forceinline__ double group8_sum(double v) {
+    v += __shfl_down(v, 4, 8);
+    v += __shfl_down(v, 2, 8);
+    v += __shfl_down(v, 1, 8);
+    return v;
 }
 
-__global__ __launch_bounds__(256) void k_eig_jacobi(const EigJob* __restrict__ jobs) {
+__device__ __forceinline__ double wave_sum(double v) {
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+template <bool LDSRES>
+__global__ __launch_bounds__(1024) void k_eig_reduce(const EigJob* __restrict__ jobs) {
+    extern __shared__ __align__(16) double dyn[];
+    __shared__ double sv[EIG_MAXN], sp[EIG_MAXN], sd[EIG_MAXN], se[EIG_MAXN], stau[EIG_MAXN];
+    __shared__ double s_lo, s_hi, s_tol, s_piv;
     const EigJob J = jobs[blockIdx.x];
     const int n = J.n;
-    double* A = J.A;
+    const int tid = threadIdx.x, lane = tid & 63;
+    double* M = LDSRES ? dyn : J.A;
+    const int ld = LDSRES ? n + 1 : n;
     double* V = J.V;
-    const int tid = threadIdx.x;
-    __shared__ double red[256];
-    __shared__ double cs[256], sn[256];
-    __shared__ int pp[256], qq[256];
-    for (int e = tid; e < n * n; e += blockDim.x) V[e] = (e / n == e % n) ? 1.0 : 0.0;
-    __syncthreads();
-    const int m = n + (n & 1);
-    const int npair = m / 2;
-    for (int sweep = 0; sweep < 60 && n > 1; ++sweep) {
-        double off = 0.0, tot = 0.0;
-        for (int e = tid; e < n * n; e += blockDim.x) {
-            const double a = A[e];
-            tot += a * a;
-            if (e / n != e % n) off += a * a;
-        }
-        off = block_sum(off, red);
-        tot = block_sum(tot, red);
-        if (off <= 1e-30 * tot || tot == 0.0) break;
-        for (int round = 0; round < m - 1; ++round) {
-            for (int k = tid; k < npair; k += blockDim.x) {
-                int p = (round + k) % (m - 1);
-                int q = (k == 0) ? (m - 1) : (round - k + m - 1) % (m - 1);
-                if (p > q) { int t = p; p = q; q = t; }
-                double c = 1.0, s = 0.0;
-                if (q < n) {
-                    const double apq = A[p * n + q];
-                    if (apq != 0.0) {
-                        const double app = A[p * n + p], aqq = A[q * n + q];
-                        const double tau = (aqq - app) / (2.0 * apq);
-                        const double tt = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
-                        c = 1.0 / sqrt(1.0 + tt * tt);
-                        s = tt * c;
-                    }
-                }
-                pp[k] = p; qq[k] = q; cs[k] = c; sn[k] = s;
-            }
-            __syncthreads();
-            // rows: A <- J^T A
-            for (int e = tid; e < npair * n; e += blockDim.x) {
-                const int k = e / n, j = e - k * n;
-                const int p = pp[k], q = qq[k];
-                if (q >= n || sn[k] == 0.0) continue;
-                const double c = cs[k], s = sn[k];
-                const double ap = A[p * n + j], aq = A[q * n + j];
-                A[p * n + j] = c * ap - s * aq;
-                A[q * n + j] = s * ap + c * aq;
-            }
-            __syncthreads();
-            // columns: A <- A J, V <- V J
-            for (int e = tid; e < npair * n; e += blockDim.x) {
-                const int k = e / n, i = e - k * n;
-                const int p = pp[k], q = qq[k];
-                if (q >= n || sn[k] == 0.0) continue;
-                const double c = cs[k], s = sn[k];
-                const double ap = A[i * n + p], aq = A[i * n + q];
-                A[i * n + p] = c * ap - s * aq;
-                A[i * n + q] = s * ap + c * aq;
-                const double vp = V[i * n + p], vq = V[i * n + q];
-                V[i * n + p] = c * vp - s * vq;
-                V[i * n + q] = s * vp + c * vq;
-            }
-            __syncthreads();
-        }
-    }
-    // eigenvalues descending (ties by index); eigenvectors into A
-    for (int i = tid; i < n; i += blockDim.x) J.w[i] = A[i * n + i];
-    __syncthreads();
-    for (int i = tid; i < n; i += blockDim.x) {
-        const double di = J.w[i];
-        int rank = 0;
-        for (int j = 0; j < n; ++j) {
-            const double dj = J.w[j];
-            rank += (dj > di) || (dj == di && j < i);
-        }
-        for (int r = 0; r < n; ++r) A[r * n + rank] = V[r * n + i];
-    }
-    __syncthreads();
-    // sorted eigenvalues: write through V's diagonal slot then back
-    for (int i = tid; i < n; i += blockDim.x) {
-        const double di = J.w[i];
-        int rank = 0;
-        for (int j = 0; j < n; ++j) {
-            const double dj = J.w[j];
-            rank += (dj > di) || (dj == di && j < i);
-        }
-        V[rank] = di;
-    }
-    __syncthreads();
-    for (int i = tid; i < n; i += blockDim.x) J.w[i] = V[i];
-}
-
-__device__ double block_sum_1024(double v, double* red16) {
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    if (lane == 0) red16[wave] = v;
-    __syncthreads();
-    double s = 0.0;
-    for (int w = 0; w < 16; ++w) s += red16[w];
-    __syncthreads();
-    return s;
-}
-
-// Round-robin Jacobi on the packed upper triangle held in LDS.  The disjoint
-// rotations of one round act on the matrix as J^T A J with J block diagonal in
-// the pair basis, so every 2x2 block formed by two pairs (k1 <= k2) is
-// updated independently: B' = G(k1) B G(k2)^T, with the diagonal blocks set
-// by the closed Jacobi form (a_pq' = 0).  One barrier per round.  The
-// transposed eigenvector matrix lives in LDS (VT_LDS) or in the job's V
-// workspace.
-__device__ __forceinline__ int tri_off(int i, int n) { return i * n - (i * (i - 1)) / 2; }
-__device__ __forceinline__ int tri_idx(int i, int j, int n) {  // i <= j
-    return tri_off(i, n) + (j - i);
-}
-
-template <bool VT_LDS>
-__global__ __launch_bounds__(1024) void k_eig_jacobi_packed(const EigJob* __restrict__ jobs) {
-    extern __shared__ double lds[];
-    const EigJob J = jobs[blockIdx.x];
-    const int n = J.n;
-    const int tid = threadIdx.x;
-    double* P = lds;                                           // n (n + 1) / 2
-    double* Vt = VT_LDS ? lds + (n * (n + 1)) / 2 : J.V;       // n x n, row p = eigenvector p
-    __shared__ double red16[16];
-    __shared__ double cs[128], sn[128];
-    __shared__ int pp[128], qq[128];
-    for (int e = tid; e < n * n; e += 1024) {
-        const int i = e / n, j = e - i * n;
-        if (i <= j) P[tri_idx(i, j, n)] = J.A[e];
-        Vt[e] = (i == j) ? 1.0 : 0.0;
-    }
-    __syncthreads();
-    const int m = n + (n & 1);
-    const int npair = m / 2;
-    for (int sweep = 0; sweep < 60 && n > 1; ++sweep) {
-        double off = 0.0, tot = 0.0;
+    if (LDSRES) {
         for (int e = tid; e < n * n; e += 1024) {
             const int i = e / n, j = e - i * n;
-            if (i > j) continue;
-            const double a = P[tri_idx(i, j, n)];
-            tot += (i == j) ? a * a : 2.0 * a * a;
-            if (i != j) off += 2.0 * a * a;
-        }
-        off = block_sum_1024(off, red16);
-        tot = block_sum_1024(tot, red16);
-        if (off <= 1e-30 * tot || tot == 0.0) break;
-        for (int round = 0; round < m - 1; ++round) {
-            if (tid < npair) {
-                const int k = tid;
-                int p = (round + k) % (m - 1);
-                int q = (k == 0) ? (m - 1) : (round - k + m - 1) % (m - 1);
-                if (p > q) { int t = p; p = q; q = t; }
-                double c = 1.0, s = 0.0;
-                if (q < n) {
-                    const double apq = P[tri_idx(p, q, n)];
-                    if (apq != 0.0) {
-                        const double app = P[tri_idx(p, p, n)], aqq = P[tri_idx(q, q, n)];
-                        const double tau = (aqq - app) / (2.0 * apq);
-                        const double tt = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
-                        c = 1.0 / sqrt(1.0 + tt * tt);
-                        s = tt * c;
-                    }
-                }
-                pp[k] = p; qq[k] = q; cs[k] = c; sn[k] = s;
-            }
-            __syncthreads();
-            // 2x2 blocks of pair-of-pairs, k1 <= k2
-            for (int b = tid; b < npair * npair; b += 1024) {
-                const int k1 = b / npair, k2 = b - k1 * npair;
-                if (k1 > k2) continue;
-                const double s1 = sn[k1], s2 = sn[k2];
-                if (s1 == 0.0 && s2 == 0.0) continue;
-                const int p1 = pp[k1], q1 = qq[k1], p2 = pp[k2], q2 = qq[k2];
-                const double c1 = cs[k1], c2 = cs[k2];
-                if (k1 == k2) {
-                    if (q1 >= n) continue;
-                    const double apq = P[tri_idx(p1, q1, n)];
-                    const double t = s1 / c1;
-                    P[tri_idx(p1, p1, n)] -= t * apq;
-                    P[tri_idx(q1, q1, n)] += t * apq;
-                    P[tri_idx(p1, q1, n)] = 0.0;
-                    continue;
-                }
-                // rows {p1, q1} (q1 may be the dummy index n), columns {p2, q2}
-                const bool r2 = q1 < n, c2ok = q2 < n;
-                auto at = [&](int i, int j) -> double& {
-                    return i <= j ? P[tri_idx(i, j, n)] : P[tri_idx(j, i, n)];
-                };
-                double b00 = at(p1, p2), b01 = c2ok ? at(p1, q2) : 0.0;
-                double b10 = r2 ? at(q1, p2) : 0.0, b11 = (r2 && c2ok) ? at(q1, q2) : 0.0;
-                // rows: G(k1) = [[c, -s], [s, c]]
-                double u00 = c1 * b00 - s1 * b10, u01 = c1 * b01 - s1 * b11;
-                double u10 = s1 * b00 + c1 * b10, u11 = s1 * b01 + c1 * b11;
-                // columns
-                double v00 = c2 * u00 - s2 * u01, v01 = s2 * u00 + c2 * u01;
-                double v10 = c2 * u10 - s2 * u11, v11 = s2 * u10 + c2 * u11;
-                at(p1, p2) = v00;
-                if (c2ok) at(p1, q2) = v01;
-                if (r2) at(q1, p2) = v10;
-                if (r2 && c2ok) at(q1, q2) = v11;
-            }
-            // eigenvector rows p, q of Vt
-            for (int e = tid; e < npair * n; e += 1024) {
-                const int k = e / n, j = e - k * n;
-                const int p = pp[k], q = qq[k];
-                if (q >= n || sn[k] == 0.0) continue;
-                const double c = cs[k], s = sn[k];
-                const double vp = Vt[p * n + j], vq = Vt[q * n + j];
-                Vt[p * n + j] = c * vp - s * vq;
-                Vt[q * n + j] = s * vp + c * vq;
-            }
-            __syncthreads();
+            M[i * ld + j] = J.A[e];
         }
     }
-    for (int i = tid; i < n; i += 1024) {
-        const double di = P[tri_idx(i, i, n)];
-        int rank = 0;
-        for (int j = 0; j < n; ++j) {
-            const double dj = P[tri_idx(j, j, n)];
-            rank += (dj > di) || (dj == di && j < i);
+    __syncthreads();
+    // ---- Householder: wave 0 forms the reflector (and stores it in V), all
+    // threads form p = tau A22 v, then every wave computes K = tau p.v / 2
+    // itself and applies A22 -= v w^T + w v^T with w = p - K v.
+    for (int k = 0; k + 2 < n; ++k) {
+        const int m = n - k - 1;
+        if (tid < 64) {
+            double part = 0.0;
+            for (int i = k + 2 + lane; i < n; i += 64) part += M[i * ld + k] * M[i * ld + k];
+            part = wave_sum(part);
+            const double alpha = M[(k + 1) * ld + k];
+            double tau = 0.0, beta = alpha, scal = 0.0;
+            if (part > 0.0) {
+                beta = -copysign(sqrt(alpha * alpha + part), alpha);
+                tau = (beta - alpha) / beta;
+                scal = 1.0 / (alpha - beta);
+            }
+            for (int i = k + 1 + lane; i < n; i += 64) {
+                const double vi = (i == k + 1) ? 1.0 : M[i * ld + k] * scal;
+                sv[i] = vi;
+                if (i >= k + 2) V[(size_t)k * n + i] = vi;
+            }
+            if (lane == 0) {
+                sd[k] = M[k * ld + k];
+                se[k] = beta;
+                stau[k] = tau;
+                V[(size_t)k * n + k] = tau;
+            }
         }
-        J.w[rank] = di;
-        for (int r = 0; r < n; ++r) J.A[r * n + rank] = Vt[i * n + r];
+        __syncthreads();
+        const double tau = stau[k];
+        if (tau == 0.0) continue;
+        for (int e = tid; e < m * 8; e += 1024) {
+            const int i = k + 1 + (e >> 3), g = e & 7;
+            double s = 0.0;
+            for (int j = k + 1 + g; j < n; j += 8) s += M[i * ld + j] * sv[j];
+            s = group8_sum(s);
+            if (g == 0) sp[i] = tau * s;
+        }
+        __syncthreads();
+        double part = 0.0;
+        for (int i = k + 1 + lane; i < n; i += 64) part += sp[i] * sv[i];
+        const double K = 0.5 * tau * wave_sum(part);
+        for (int e = tid; e < m * m; e += 1024) {
+            const int i = k + 1 + e / m, j = k + 1 + e % m;
+            const double vi = sv[i], vj = sv[j];
+            M[i * ld + j] -= vi * (sp[j] - K * vj) + (sp[i] - K * vi) * vj;
+        }
+        __syncthreads();
+    }
+    if (tid == 0) {
+        if (n >= 2) {
+            sd[n - 2] = M[(n - 2) * ld + (n - 2)];
+            se[n - 2] = M[(n - 1) * ld + (n - 2)];
+        }
+        sd[n - 1] = M[(n - 1) * ld + (n - 1)];
+        se[n - 1] = 0.0;
+    }
+    __syncthreads();
+    for (int i = tid; i < n; i += 1024) {
+        J.t[i] = sd[i];
+        J.t[n + i] = se[i];
+    }
+    // ---- Gershgorin bracket, pivot guard and tolerance (wave 0); sp <- e^2
+    if (tid < 64) {
+        double lo = 1e308, hi = -1e308, e2max = 0.0;
+        for (int i = lane; i < n; i += 64) {
+            const double ea = i > 0 ? fabs(se[i - 1]) : 0.0, eb = fabs(se[i]);
+            lo = fmin(lo, sd[i] - ea - eb);
+            hi = fmax(hi, sd[i] + ea + eb);
+            e2max = fmax(e2max, se[i] * se[i]);
+        }
+        for (int off = 32; off > 0; off >>= 1) {
+            lo = fmin(lo, __shfl_xor(lo, off, 64));
+            hi = fmax(hi, __shfl_xor(hi, off, 64));
+            e2max = fmax(e2max, __shfl_xor(e2max, off, 64));
+        }
+        if (lane == 0) {
+            const double tn = fmax(fabs(lo), fabs(hi));
+            const double piv = 2.2250738585072014e-308 * fmax(1.0, e2max);
+            const double fudge = 2.1 * tn * EIG_EPS * n + 4.2 * piv;
+            s_lo = lo - fudge;
+            s_hi = hi + fudge;
+            s_tol = EIG_EPS * tn;
+            s_piv = piv;
+        }
+    }
+    for (int i = tid; i < n; i += 1024) sp[i] = se[i] * se[i];
+    __syncthreads();
+    // ---- multisection
+    int L = 64;
+    while (L > 1 && L * n > 1024) L >>= 1;
+    const int u = tid % L, j = tid / L;
+    const double piv = s_piv, tol = s_tol;
+    double lo = s_lo, hi = s_hi;
+    bool done = j >= n;
+    for (int it = 0; it < 400; ++it) {
+        if (!done && hi - lo <= fmax(tol, 2.0 * EIG_EPS * fmax(fabs(lo), fabs(hi)))) done = true;
+        if (__ballot(!done) == 0) break;
+        const double step = (hi - lo) / (L + 1);
+        int cnt = 0;
+        if (!done) {
+            const double x = lo + (u + 1) * step;
+            double q = sd[0] - x;
+            if (fabs(q) <= piv) q = -piv;
+            cnt = q < 0.0;
+            for (int i = 1; i < n; ++i) {
+                q = sd[i] - x - sp[i - 1] / q;
+                if (fabs(q) <= piv) q = -piv;
+                cnt += q < 0.0;
+            }
+        }
+        const unsigned long long bal = __ballot(!done && cnt > j);
+        const int base = lane - u;
+        const unsigned long long mask = L == 64 ? ~0ull : ((1ull << L) - 1);
+        const unsigned long long gb = (bal >> base) & mask;
+        const int us = gb ? __ffsll((long long)gb) - 1 : L;  // first point whose count exceeds j
+        if (!done) {
+            const double nlo = us == 0 ? lo : lo + us * step;
+            const double nhi = us == L ? hi : lo + (us + 1) * step;
+            lo = nlo;
+            hi = nhi;
+        }
+    }
+    if (j < n && u == 0) J.w[n - 1 - j] = 0.5 * (lo + hi);
+}
+
+__device__ __forceinline__ unsigned long long mix64(unsigned long long z) {
+    z += 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+// Solves (T - sigma I) y = y in place by Gaussian elimination with partial
+// pivoting (pivots below `guard` in magnitude are raised to it); U's rows go to
+// the thread's scratch columns.  Y(i) addresses the vector.
+template <class YA>
+__device__ void tri_solve(const double* sd, const double* se, int n, double sigma, double guard, YA Y,
+                          double* U, int ustride) {
+    double bi = sd[0] - sigma, ci = n > 1 ? se[0] : 0.0, yi = Y(0);
+    for (int i = 0; i + 1 < n; ++i) {
+        const double a1 = se[i], b1 = sd[i + 1] - sigma, c1 = i + 2 < n ? se[i + 1] : 0.0, y1 = Y(i + 1);
+        double* Ui = U + (size_t)3 * i * ustride;
+        if (fabs(bi) >= fabs(a1)) {
+            if (fabs(bi) < guard) bi = bi < 0.0 ? -guard : guard;
+            const double f = a1 / bi;
+            Ui[0] = bi;
+            Ui[ustride] = ci;
+            Ui[2 * ustride] = 0.0;
+            Y(i) = yi;
+            bi = b1 - f * ci;
+            ci = c1;
+            yi = y1 - f * yi;
+        } else {
+            const double f = bi / a1;
+            Ui[0] = a1;
+            Ui[ustride] = b1;
+            Ui[2 * ustride] = c1;
+            Y(i) = y1;
+            const double nb = ci - f * b1, nc = -f * c1, ny = yi - f * y1;
+            bi = nb;
+            ci = nc;
+            yi = ny;
+        }
+    }
+    if (fabs(bi) < guard) bi = bi < 0.0 ? -guard : guard;
+    double y2 = 0.0, y1 = yi / bi;
+    Y(n - 1) = y1;
+    for (int i = n - 2; i >= 0; --i) {
+        const double* Ui = U + (size_t)3 * i * ustride;
+        const double y0 = (Y(i) - Ui[ustride] * y1 - Ui[2 * ustride] * y2) / Ui[0];
+        Y(i) = y0;
+        y2 = y1;
+        y1 = y0;
+    }
+}
+
+template <bool LDSRES>
+__global__ __launch_bounds__(1024) void k_eig_vectors(const EigJob* __restrict__ jobs, int* __restrict__ status) {
+    extern __shared__ __align__(16) double dyn[];
+    __shared__ double sd[EIG_MAXN], se[EIG_MAXN], sw[EIG_MAXN], sv[EIG_MAXN], sv2[EIG_MAXN], sp[EIG_MAXN];
+    __shared__ int s_fail;
+    const EigJob J = jobs[blockIdx.x];
+    const int n = J.n, k = J.k;
+    if (k <= 0) return;
+    const int tid = threadIdx.x, lane = tid & 63;
+    // Y (n x k): LDS row major with rows padded to k + 1, or the first k
+    // columns of A
+    const int ldy = LDSRES ? k + 1 : n;
+    double* Yb = LDSRES ? dyn : J.A;
+    double* U = J.t + 2 * n;              // 3 n k
+    double* G = U + (size_t)3 * n * k;   // k x k
+    for (int i = tid; i < n; i += 1024) {
+        sd[i] = J.t[i];
+        se[i] = J.t[n + i];
+    }
+    for (int i = tid; i < k; i += 1024) sw[i] = J.w[i];
+    if (tid == 0) s_fail = 0;
+    __syncthreads();
+    const double tnorm = fmax(fabs(J.w[0]), fabs(J.w[n - 1]));
+    const double guard = tnorm > 0.0 ? EIG_EPS * tnorm : 2.2250738585072014e-308;
+    const double tight = 1000.0 * EIG_EPS * tnorm;
+    // ---- inverse iteration; a cluster of eigenvalues closer than `tight`
+    // is done in order by its first thread, each vector kept orthogonal to
+    // the cluster's earlier ones
+    if (tid < k) {
+        int j0 = tid;
+        if (j0 == 0 || sw[j0 - 1] - sw[j0] > tight) {
+            int j1 = j0;
+            while (j1 + 1 < k && sw[j1] - sw[j1 + 1] <= tight) ++j1;
+            for (int c = j0; c <= j1; ++c) {
+                auto Yc = [&](int i) -> double& { return Yb[(size_t)i * ldy + c]; };
+                for (int i = 0; i < n; ++i) {
+                    const unsigned long long h = mix64(((unsigned long long)c << 32) ^ (unsigned long long)i);
+                    Yc(i) = (double)(h >> 11) * (2.0 / 9007199254740992.0) - 1.0;
+                }
+                for (int pass = 0; pass < 4; ++pass) {
+                    for (int c2 = j0; c2 < c; ++c2) {  // against the cluster's earlier vectors
+                        double dotv = 0.0;
+                        for (int i = 0; i < n; ++i) dotv += Yb[(size_t)i * ldy + c2] * Yc(i);
+                        for (int i = 0; i < n; ++i) Yc(i) -= dotv * Yb[(size_t)i * ldy + c2];
+                    }
+                    if (pass < 3) tri_solve(sd, se, n, sw[c], guard, Yc, U + c, k);
+                    double nrm = 0.0;
+                    for (int i = 0; i < n; ++i) nrm += Yc(i) * Yc(i);
+                    const double s = nrm > 0.0 ? 1.0 / sqrt(nrm) : 0.0;
+                    for (int i = 0; i < n; ++i) Yc(i) *= s;
+                }
+            }
+        }
+    }
+    __syncthreads();
+    // ---- two passes of Cholesky QR: G = Y^T Y = R^T R, Y <- Y R^-1
+    const int T4 = (k + 3) / 4, ntile = T4 * (T4 + 1) / 2;
+    for (int pass = 0; pass < 2; ++pass) {
+        for (int t = tid; t < ntile; t += 1024) {
+            int ta = 0, rem = t;
+            while (rem >= T4 - ta) { rem -= T4 - ta; ++ta; }
+            const int tb = ta + rem, a0 = ta * 4, b0 = tb * 4;
+            double acc[4][4] = {};
+            for (int i = 0; i < n; ++i) {
+                double ya[4], yb[4];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    ya[q] = a0 + q < k ? Yb[(size_t)i * ldy + a0 + q] : 0.0;
+                    yb[q] = b0 + q < k ? Yb[(size_t)i * ldy + b0 + q] : 0.0;
+                }
+#pragma unroll
+                for (int p = 0; p < 4; ++p)
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) acc[p][q] += ya[p] * yb[q];
+            }
+#pragma unroll
+            for (int p = 0; p < 4; ++p)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int a = a0 + p, b = b0 + q;
+                    if (a < k && b < k && a <= b) G[(size_t)a * k + b] = acc[p][q];
+                }
+        }
+        __syncthreads();
+        // upper Cholesky factor in place, wave 0
+        if (tid < 64) {
+            for (int c = 0; c < k; ++c) {
+                const double pv = G[(size_t)c * k + c];
+                if (!(pv > 1e-24)) {
+                    if (lane == 0) s_fail = 1;
+                    break;
+                }
+                const double r = sqrt(pv), ri = 1.0 / r;
+                for (int l = c + 1 + lane; l < k; l += 64) G[(size_t)c * k + l] *= ri;
+                __threadfence_block();
+                if (lane == 0) G[(size_t)c * k + c] = r;
+                const int m = k - c - 1;
+                for (int e = lane; e < m * m; e += 64) {
+                    const int i = c + 1 + e / m, l = c + 1 + e % m;
+                    if (l >= i) G[(size_t)i * k + l] -= G[(size_t)c * k + i] * G[(size_t)c * k + l];
+                }
+                __threadfence_block();
+            }
+        }
+        __syncthreads();
+        if (s_fail) break;
+        // rows of Y: x R = y by forward substitution
+        for (int i = tid; i < n; i += 1024) {
+            double* yr = Yb + (size_t)i * ldy;
+            for (int l = 0; l < k; ++l) {
+                double s = yr[l];
+                for (int m2 = 0; m2 < l; ++m2) s -= yr[m2] * G[(size_t)m2 * k + l];
+                yr[l] = s / G[(size_t)l * k + l];
+            }
+        }
+        __syncthreads();
+    }
+    if (s_fail) {
+        if (tid == 0) atomicAdd(status, 1);
+        return;
+    }
+    // ---- back-transform: Y <- H_0 H_1 ... H_{n-3} Y, the next reflector
+    // staged while the current one is applied
+    const double* V = J.V;
+    auto stage = [&](int r, double* dst) {
+        for (int i = r + 1 + tid; i < n; i += 1024) dst[i] = (i == r + 1) ? 1.0 : V[(size_t)r * n + i];
+    };
+    if (n >= 3) stage(n - 3, sv);
+    __syncthreads();
+    double* vcur = sv;
+    double* vnext = sv2;
+    for (int r = n - 3; r >= 0; --r) {
+        const double tau = V[(size_t)r * n + r];
+        const int m = n - r - 1;
+        if (tau != 0.0) {
+            for (int e = tid; e < k * 8; e += 1024) {
+                const int l = e >> 3, g = e & 7;
+                double s = 0.0;
+                for (int i = r + 1 + g; i < n; i += 8) s += vcur[i] * Yb[(size_t)i * ldy + l];
+                s = group8_sum(s);
+                if (g == 0) sp[l] = tau * s;
+            }
+            __syncthreads();
+            for (int e = tid; e < m * k; e += 1024) {
+                const int i = r + 1 + e / k, l = e % k;
+                Yb[(size_t)i * ldy + l] -= vcur[i] * sp[l];
+            }
+        }
+        if (r > 0) stage(r - 1, vnext);
+        __syncthreads();
+        double* t = vcur;
+        vcur = vnext;
+        vnext = t;
+    }
+    if (LDSRES) {
+        for (int e = tid; e < n * k; e += 1024) {
+            const int i = e / k, l = e % k;
+            J.A[(size_t)i * n + l] = Yb[(size_t)i * ldy + l];
+        }
     }
 }
 
@@ -523,23 +672,17 @@ void set_device(int device, void* stream) {
     if (std::string(prop.gcnArchName).rfind("gfx950", 0) != 0)
         throw Error{MPSPT_E_NODEV, std::string("device is ") + prop.gcnArchName + ", the library is built for gfx950"};
     g_stream = static_cast<hipStream_t>(stream);
-    // dynamic LDS available to the eigensolver next to ~4 KB of static shared memory;
-    // the packed upper triangle (n (n + 1) / 2 doubles) must fit
+    // dynamic LDS left for the eigensolver's matrix (or basis) next to its
+    // ~25 KB of static shared memory
     int lds = 0;
     check(hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, device), "hipDeviceGetAttribute");
-    const long budget = (long)lds - 4096;
-    g_lds_budget = budget > 0 ? (size_t)budget : 0;
-    int nmax = 0;
-    while ((long)(nmax + 1) * (nmax + 2) / 2 * 8 <= budget && nmax < 255) ++nmax;
-    if (budget > 65536 - 4096) {
-        check(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_eig_jacobi_packed<true>),
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)budget),
-              "hipFuncSetAttribute");
-        check(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_eig_jacobi_packed<false>),
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)budget),
-              "hipFuncSetAttribute");
-    }
-    g_eig_lds_max = nmax;
+    const long budget = ((long)lds - 6 * EIG_MAXN * 8 - 1024) / 16 * 16;
+    if (budget < 4096) throw Error{MPSPT_E_NODEV, "not enough LDS for the eigensolver"};
+    g_lds_budget = (size_t)budget;
+    const void* ks[] = {reinterpret_cast<const void*>(&k_eig_reduce<true>),
+                        reinterpret_cast<const void*>(&k_eig_vectors<true>)};
+    for (const void* f : ks)
+        check(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)budget), "hipFuncSetAttribute");
 }
 
 // Stream-ordered caching allocator.  All device work of the library is issued
@@ -708,31 +851,36 @@ void diag_grouped(const DiagGroup* groups, int ngroups, const DiagTerm* terms) {
     hipLaunchKernelGGL(k_diag_grouped, dim3(ngroups), dim3(256), 0, g_stream, groups, terms);
     check(hipGetLastError(), "k_diag_grouped");
 }
-void eig_batched(const EigJob* jobs, int njobs, int nmax) {
+void eig_reduce(const EigJob* jobs, int njobs, int nmax) {
     if (njobs <= 0) return;
+    if (nmax > EIG_MAXN) throw Error{MPSPT_E_ARG, "eigensolver limited to n <= 512"};
     Prof p(K_EIG, 0, 0);
-    const size_t packed = (size_t)nmax * (nmax + 1) / 2 * sizeof(double);
-    const size_t vt = (size_t)nmax * nmax * sizeof(double);
-    if (packed + vt <= g_lds_budget) {
-        hipLaunchKernelGGL(k_eig_jacobi_packed<true>, dim3(njobs), dim3(1024), packed + vt, g_stream, jobs);
-        check(hipGetLastError(), "k_eig_jacobi_packed");
-    } else if (packed <= g_lds_budget) {
-        hipLaunchKernelGGL(k_eig_jacobi_packed<false>, dim3(njobs), dim3(1024), packed, g_stream, jobs);
-        check(hipGetLastError(), "k_eig_jacobi_packed");
+    if (eig_reduce_class(nmax) == 0) {
+        const size_t shm = (size_t)nmax * (nmax + 1) * sizeof(double);
+        hipLaunchKernelGGL(k_eig_reduce<true>, dim3(njobs), dim3(1024), shm, g_stream, jobs);
     } else {
-        hipLaunchKernelGGL(k_eig_jacobi, dim3(njobs), dim3(256), 0, g_stream, jobs);
-        check(hipGetLastError(), "k_eig_jacobi");
+        hipLaunchKernelGGL(k_eig_reduce<false>, dim3(njobs), dim3(1024), 0, g_stream, jobs);
     }
+    check(hipGetLastError(), "k_eig_reduce");
 }
-int eig_class(int n) {
-    const size_t packed = (size_t)n * (n + 1) / 2 * sizeof(double);
-    const size_t vt = (size_t)n * n * sizeof(double);
-    if (packed + vt <= g_lds_budget) return 0;
-    if (packed <= g_lds_budget) return 1;
-    return 2;
+void eig_vectors(const EigJob* jobs, int njobs, int nmax, int kmax, int* status) {
+    if (njobs <= 0) return;
+    if (nmax > EIG_MAXN || kmax > nmax) throw Error{MPSPT_E_ARG, "eigensolver limited to k <= n <= 512"};
+    Prof p(K_EIGV, 0, 0);
+    if (eig_vectors_class(nmax, kmax) == 0) {
+        const size_t shm = (size_t)nmax * (kmax + 1) * sizeof(double);
+        hipLaunchKernelGGL(k_eig_vectors<true>, dim3(njobs), dim3(1024), shm, g_stream, jobs, status);
+    } else {
+        hipLaunchKernelGGL(k_eig_vectors<false>, dim3(njobs), dim3(1024), 0, g_stream, jobs, status);
+    }
+    check(hipGetLastError(), "k_eig_vectors");
 }
+int eig_reduce_class(int n) { return (size_t)n * (n + 1) * sizeof(double) <= g_lds_budget ? 0 : 1; }
+int eig_vectors_class(int n, int k) { return (size_t)n * (k + 1) * sizeof(double) <= g_lds_budget ? 0 : 1; }
+size_t eig_work(int n) { return 2 * (size_t)n + 4 * (size_t)n * n; }
 
 void dot(const double* a, const double* b, size_t n, double* scal, int slot, double* partials) {
+    Prof pr(K_VEC, 2.0 * n, 16.0 * n);
     const int nb = n_blocks(n);
     hipLaunchKernelGGL(k_dot_partial, dim3(nb), dim3(RED_THREADS), 0, g_stream, a, b, n, partials);
     hipLaunchKernelGGL(k_reduce, dim3(1), dim3(RED_THREADS), 0, g_stream, partials, nb, 0, scal, slot, -1);
@@ -741,6 +889,7 @@ void dot(const double* a, const double* b, size_t n, double* scal, int slot, dou
 void cg_init(double* r, double* z, double* p, const double* b, const double* q, const double* d, size_t n,
              double* scal, double* partials) {
     const int nb = std::min(n_blocks(n), kPartials / 3);
+    Prof pr(K_VEC, 6.0 * n, 48.0 * n);
     const int stride = kPartials / 3;
     hipLaunchKernelGGL(k_cg_init, dim3(nb), dim3(RED_THREADS), 0, g_stream, r, z, p, b, q, d, n, partials, stride);
     hipLaunchKernelGGL(k_reduce, dim3(1), dim3(RED_THREADS), 0, g_stream, partials, nb, stride, scal, (int)S_RZ0,
@@ -750,6 +899,7 @@ void cg_init(double* r, double* z, double* p, const double* b, const double* q, 
     check(hipGetLastError(), "cg_init");
 }
 void cg_shift_dot(double* q, const double* p, double shift, size_t n, double* scal, double* partials) {
+    Prof pr(K_VEC, 4.0 * n, 24.0 * n);
     const int nb = n_blocks(n);
     hipLaunchKernelGGL(k_shift_dot, dim3(nb), dim3(RED_THREADS), 0, g_stream, q, p, shift, n, partials);
     hipLaunchKernelGGL(k_reduce, dim3(1), dim3(RED_THREADS), 0, g_stream, partials, nb, 0, scal, (int)S_PQ, -1);
@@ -757,6 +907,7 @@ void cg_shift_dot(double* q, const double* p, double shift, size_t n, double* sc
 }
 void cg_update(double* x, double* r, double* z, const double* p, const double* q, const double* d, size_t n,
                double* scal, int rz_cur, int rz_new, double* partials) {
+    Prof pr(K_VEC, 9.0 * n, 64.0 * n);
     const int nb = n_blocks(n);
     const int stride = kPartials / 2;
     hipLaunchKernelGGL(k_cg_update, dim3(nb), dim3(RED_THREADS), 0, g_stream, x, r, z, p, q, d, n, scal, rz_cur,
@@ -766,18 +917,21 @@ void cg_update(double* x, double* r, double* z, const double* p, const double* q
     check(hipGetLastError(), "cg_update");
 }
 void cg_direction(double* p, const double* z, size_t n, const double* scal, int rz_cur, int rz_new) {
+    Prof pr(K_VEC, 2.0 * n, 24.0 * n);
     const int nb = n_blocks(n);
     hipLaunchKernelGGL(k_cg_direction, dim3(nb), dim3(RED_THREADS), 0, g_stream, p, z, n, scal, rz_cur, rz_new);
     check(hipGetLastError(), "cg_direction");
 }
 void davidson_precond(double* t, const double* r, const double* d, double theta, size_t n) {
     if (!n) return;
+    Prof pr(K_VEC, 3.0 * n, 24.0 * n);
     const int nb = n_blocks(n);
     hipLaunchKernelGGL(k_dav_precond, dim3(nb), dim3(RED_THREADS), 0, g_stream, t, r, d, theta, n);
     check(hipGetLastError(), "davidson_precond");
 }
 void axpby(double* y, const double* x, double a, double b, size_t n) {
     if (!n) return;
+    Prof pr(K_VEC, 3.0 * n, 24.0 * n);
     const int nb = n_blocks(n);
     hipLaunchKernelGGL(k_axpby, dim3(nb), dim3(RED_THREADS), 0, g_stream, y, x, a, b, n);
     check(hipGetLastError(), "axpby");

@@ -190,7 +190,8 @@ class Context:
     def profile(self, enable=True):
         self._ok(self.lib.mpspt_profile(self.h, int(bool(enable))))
 
-    KERNELS = {0: "k_gemm_grouped", 1: "k_axpy_grouped", 2: "k_eig_jacobi", 3: "k_diag_grouped"}
+    KERNELS = {0: "k_gemm_grouped", 1: "k_axpy_grouped", 2: "k_eig_reduce", 3: "k_diag_grouped", 4: "k_eig_vectors",
+               5: "vector kernels"}
 
     def kernel_stats(self, kind):
         s, n, f, b = C.c_double(), C.c_int64(), C.c_double(), C.c_double()

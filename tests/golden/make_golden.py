@@ -51,10 +51,12 @@ def main(out):
                e_fci=e_fci, e0=sw.E0, e2_exact=e2_exact, e2_sweep=sw.e_sweep, e3=e3,
                trace=[dict(sweep=t["sweep"], dir=t["dir"], window=t["window"], e2=t["e2"],
                            cg_iters=t["cg_iters"], discarded=t["discarded"]) for t in sw.trace],
-               bonds=[[[q[0], q[1], d] for q, d in b] for b in sw.bonds()],
-               psi0_bonds=[[[q[0], q[1], d] for q, d in b] for b in psi0[0]])
-    with open(out, "w") as f:
+               bonds=[[[int(q[0]), int(q[1]), int(d)] for q, d in b] for b in sw.bonds()],
+               psi0_bonds=[[[int(q[0]), int(q[1]), int(d)] for q, d in b] for b in psi0[0]])
+    tmp = out + ".tmp"
+    with open(tmp, "w") as f:
         json.dump(res, f, indent=1)
+    os.replace(tmp, out)
 
 
 if __name__ == "__main__":
