@@ -13,7 +13,9 @@
 namespace mpspt {
 namespace dev {
 
-// C (m x n, leading dimension ldc) [+]= sum_t alpha_t op(A_t) op(B_t)
+// C (m x n, leading dimension ldc) [+]= sum_t alpha_t op(A_t) op(B_t), computed in
+// GEMM_TILE x GEMM_TILE output tiles
+constexpr int GEMM_TILE = 16;
 struct GemmTerm {
     const double* A;
     const double* B;

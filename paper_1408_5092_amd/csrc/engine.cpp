@@ -21,7 +21,7 @@ namespace mpspt {
 
 namespace {
 dev::Error err(int code, const std::string& m) { return dev::Error{code, m}; }
-constexpr int kTile = 32;
+constexpr int kTile = dev::GEMM_TILE;
 
 // Output blocks of an environment update keyed by (channel, bra sector) and
 // visited in ascending key order.
@@ -208,17 +208,104 @@ void GemmBatch::term(const double* A, int lda, bool tA, const double* B, int ldb
     flops_ += 2.0 * g.m * g.n * k;
     bytes_ += 8.0 * ((double)g.m * k + (double)k * g.n);
 }
+// Groups whose summed k is long compared with the launch's work are split
+// into segments (at term boundaries, or inside a long term) that write
+// partial products to scratch; a grouped axpy then adds the segments into C
+// in order, so the result stays deterministic.
 void GemmBatch::upload() {
-    std::vector<dev::GemmGroup> keep;
-    keep.reserve(g_.size());
-    for (auto& g : g_)
-        if (g.tile0 >= 0) keep.push_back(g);
-    g_.swap(keep);
+    if (split_) {  // already laid out
+        dg_.upload(g_);
+        dt_.upload(t_);
+        red_.upload();
+        return;
+    }
+    split_ = true;
+    std::vector<dev::GemmGroup> live;
+    live.reserve(g_.size());
+    double work = 0;
+    for (auto& g : g_) {
+        if (g.tile0 < 0) continue;
+        long K = 0;
+        for (int t = 0; t < g.nterms; ++t) K += t_[g.term0 + t].k;
+        const int tl = ((g.m + kTile - 1) / kTile) * ((g.n + kTile - 1) / kTile);
+        work += (double)tl * K;
+        live.push_back(g);
+    }
+    const long kseg = std::max<long>(512, (long)(work / 8192.0));
+    size_t psz = 0;
+    std::vector<int> nseg(live.size(), 1);
+    for (size_t gi = 0; gi < live.size(); ++gi) {
+        const auto& g = live[gi];
+        long K = 0;
+        for (int t = 0; t < g.nterms; ++t) K += t_[g.term0 + t].k;
+        if (K > kseg) {
+            nseg[gi] = (int)((K + kseg - 1) / kseg);
+            psz += (size_t)nseg[gi] * g.m * g.n;
+        }
+    }
+    part_.ensure(std::max<size_t>(psz, 1));
+    red_.clear();
+    std::vector<dev::GemmGroup> gs;
+    std::vector<dev::GemmTerm> ts;
+    gs.reserve(live.size());
+    ts.reserve(t_.size());
+    int tiles = 0;
+    size_t poff = 0;
+    for (size_t gi = 0; gi < live.size(); ++gi) {
+        const auto& g = live[gi];
+        const int tl = ((g.m + kTile - 1) / kTile) * ((g.n + kTile - 1) / kTile);
+        if (nseg[gi] == 1) {
+            dev::GemmGroup c = g;
+            c.term0 = (int)ts.size();
+            c.tile0 = tiles;
+            tiles += tl;
+            for (int t = 0; t < g.nterms; ++t) ts.push_back(t_[g.term0 + t]);
+            gs.push_back(c);
+            continue;
+        }
+        long K = 0;
+        for (int t = 0; t < g.nterms; ++t) K += t_[g.term0 + t].k;
+        const long per = (K + nseg[gi] - 1) / nseg[gi];
+        red_.group(g.C, g.ldc, g.m, g.n, g.accumulate != 0);
+        dev::GemmGroup cur{part_.p + poff, g.n, g.m, g.n, (int)ts.size(), 0, 0, tiles};
+        long used = 0;
+        auto close = [&]() {
+            if (cur.nterms == 0) return;
+            gs.push_back(cur);
+            tiles += tl;
+            red_.term(cur.C, g.n, false, 1.0);
+            poff += (size_t)g.m * g.n;
+            cur = dev::GemmGroup{part_.p + poff, g.n, g.m, g.n, (int)ts.size(), 0, 0, tiles};
+            used = 0;
+        };
+        for (int t = 0; t < g.nterms; ++t) {
+            dev::GemmTerm tm = t_[g.term0 + t];
+            int k0 = 0;
+            while (k0 < tm.k) {
+                const int take = (int)std::min<long>(tm.k - k0, per - used);
+                dev::GemmTerm sub = tm;
+                sub.A = tm.A + (size_t)k0 * (tm.transA ? (size_t)tm.lda : 1);
+                sub.B = tm.B + (size_t)k0 * (tm.transB ? 1 : (size_t)tm.ldb);
+                sub.k = take;
+                ts.push_back(sub);
+                ++cur.nterms;
+                used += take;
+                k0 += take;
+                if (used >= per) close();
+            }
+        }
+        close();
+    }
+    g_.swap(gs);
+    t_.swap(ts);
+    tiles_ = tiles;
     dg_.upload(g_);
     dt_.upload(t_);
+    red_.upload();
 }
 void GemmBatch::run() const {
     if (tiles_ > 0) dev::gemm_grouped(dg_.p, (int)g_.size(), dt_.p, tiles_, flops_, bytes_);
+    red_.run();
 }
 
 void AxpyBatch::group(double* dst, int ldd, int m, int n, bool acc) {

@@ -117,28 +117,7 @@ struct TwoOp {
 };
 TwoOp make_twoop(const MPO& m, int i);
 
-// Work list of grouped GEMMs, reusable across launches.
-class GemmBatch {
-  public:
-    void clear() { g_.clear(); t_.clear(); tiles_ = 0; flops_ = 0; bytes_ = 0; }
-    void group(double* C, int ldc, int m, int n, bool acc);
-    void term(const double* A, int lda, bool tA, const double* B, int ldb, bool tB, int k, double alpha);
-    void upload();
-    void run() const;
-    bool empty() const { return g_.empty(); }
-    double flops() const { return flops_; }
-    double bytes() const { return bytes_; }  // operand blocks read once, output blocks written once
-    size_t nterms() const { return t_.size(); }
-
-  private:
-    std::vector<dev::GemmGroup> g_;
-    std::vector<dev::GemmTerm> t_;
-    DevArr<dev::GemmGroup> dg_;
-    DevArr<dev::GemmTerm> dt_;
-    int tiles_ = 0;
-    double flops_ = 0, bytes_ = 0;
-};
-
+// Work list of grouped block axpys, reusable across launches.
 class AxpyBatch {
   public:
     void clear() { g_.clear(); t_.clear(); flops_ = 0; bytes_ = 0; }
@@ -157,6 +136,32 @@ class AxpyBatch {
     DevArr<dev::AxpyTerm> dt_;
     double flops_ = 0, bytes_ = 0;
 };
+
+// Work list of grouped GEMMs, reusable across launches.
+class GemmBatch {
+  public:
+    void clear() { g_.clear(); t_.clear(); tiles_ = 0; flops_ = 0; bytes_ = 0; red_.clear(); split_ = false; }
+    void group(double* C, int ldc, int m, int n, bool acc);
+    void term(const double* A, int lda, bool tA, const double* B, int ldb, bool tB, int k, double alpha);
+    void upload();
+    void run() const;
+    bool empty() const { return g_.empty(); }
+    double flops() const { return flops_; }
+    double bytes() const { return bytes_; }  // operand blocks read once, output blocks written once
+    size_t nterms() const { return t_.size(); }
+
+  private:
+    std::vector<dev::GemmGroup> g_;
+    std::vector<dev::GemmTerm> t_;
+    DevArr<dev::GemmGroup> dg_;
+    DevArr<dev::GemmTerm> dt_;
+    int tiles_ = 0;
+    double flops_ = 0, bytes_ = 0;
+    AxpyBatch red_;  // sums split-k partials into the outputs
+    DevBuf part_;
+    bool split_ = false;
+};
+
 
 // y = sum L (x) O (x) R applied to x (three grouped launches).
 struct EffOp {

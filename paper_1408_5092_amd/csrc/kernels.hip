@@ -35,74 +35,68 @@ void check(hipError_t e, const char* what) {
     }
 }
 
-constexpr int TILE = 32;
-constexpr int KC = 16;
 constexpr int RED_THREADS = 256;
 
 typedef double d4 __attribute__((ext_vector_type(4)));
 
 // ------------------------------------------------------------------- GEMM
+// One wave per 16 x 16 output tile (four tiles per workgroup, possibly of
+// different groups), no LDS and no barriers: each lane loads its MFMA
+// operands straight from global memory (A row lane%16 / B column lane%16,
+// k = lane/16 + 4 s), four k-steps of loads in flight per iteration, so a
+// group's terms run back to back without synchronisation.  Rows, columns
+// and k beyond the block are loaded as zeros.
 __global__ __launch_bounds__(256) void k_gemm_grouped(const GemmGroup* __restrict__ G, int ngroups,
-                                                      const GemmTerm* __restrict__ T) {
-    const int bid = blockIdx.x;
+                                                      const GemmTerm* __restrict__ T, int ntiles) {
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int tile = blockIdx.x * 4 + wave;
+    if (tile >= ntiles) return;
     int lo = 0, hi = ngroups - 1;
     while (lo < hi) {
-        int mid = (lo + hi + 1) >> 1;
-        if (G[mid].tile0 <= bid) lo = mid;
+        const int mid = (lo + hi + 1) >> 1;
+        if (G[mid].tile0 <= tile) lo = mid;
         else hi = mid - 1;
     }
     const GemmGroup g = G[lo];
-    const int tiles_n = (g.n + TILE - 1) / TILE;
-    const int t = bid - g.tile0;
-    const int row0 = (t / tiles_n) * TILE;
-    const int col0 = (t % tiles_n) * TILE;
-
-    __shared__ double As[KC][TILE + 1];  // op(A)[row0 + i][k0 + kk] at As[kk][i]
-    __shared__ double Bs[KC][TILE + 1];  // op(B)[k0 + kk][col0 + j] at Bs[kk][j]
-    const int tid = threadIdx.x;
-    const int wave = tid >> 6, lane = tid & 63;
-    const int wm = (wave >> 1) * 16, wn = (wave & 1) * 16;
+    const int tiles_n = (g.n + GEMM_TILE - 1) / GEMM_TILE;
+    const int t = tile - g.tile0;
+    const int row0 = (t / tiles_n) * GEMM_TILE, col0 = (t % tiles_n) * GEMM_TILE;
+    const int li = lane & 15, lk = lane >> 4;
+    const int ar = row0 + li, bc = col0 + li;
+    const bool aok = ar < g.m, bok = bc < g.n;
     d4 acc = {0.0, 0.0, 0.0, 0.0};
-
     for (int ti = 0; ti < g.nterms; ++ti) {
         const GemmTerm tm = T[g.term0 + ti];
-        for (int k0 = 0; k0 < tm.k; k0 += KC) {
-            // A tile: 32 x 16 values, two per thread
-            for (int e = tid; e < TILE * KC; e += 256) {
-                int i, kk;
-                if (tm.transA) { i = e % TILE; kk = e / TILE; }
-                else { kk = e % KC; i = e / KC; }
-                const int gi = row0 + i, gk = k0 + kk;
-                double v = 0.0;
-                if (gi < g.m && gk < tm.k)
-                    v = tm.transA ? tm.A[(size_t)gk * tm.lda + gi] : tm.A[(size_t)gi * tm.lda + gk];
-                As[kk][i] = v;
-            }
-            for (int e = tid; e < TILE * KC; e += 256) {
-                int j, kk;
-                if (tm.transB) { kk = e % KC; j = e / KC; }
-                else { j = e % TILE; kk = e / TILE; }
-                const int gj = col0 + j, gk = k0 + kk;
-                double v = 0.0;
-                if (gj < g.n && gk < tm.k)
-                    v = tm.transB ? tm.B[(size_t)gj * tm.ldb + gk] : tm.B[(size_t)gk * tm.ldb + gj];
-                Bs[kk][j] = v * tm.alpha;
-            }
-            __syncthreads();
+        // element (row, kk) of op(A) at pa[kk * sa]; element (kk, col) of op(B) at pb[kk * sb]
+        const double* pa = tm.transA ? tm.A + ar : tm.A + (size_t)ar * tm.lda;
+        const size_t sa = tm.transA ? (size_t)tm.lda : 1;
+        const double* pb = tm.transB ? tm.B + (size_t)bc * tm.ldb : tm.B + bc;
+        const size_t sb = tm.transB ? 1 : (size_t)tm.ldb;
+        const double alpha = tm.alpha;
+        const int k = tm.k;
+        int k0 = 0;
+        for (; k0 + 16 <= k; k0 += 16) {
+            double a[4], b[4];
 #pragma unroll
-            for (int kk = 0; kk < KC; kk += 4) {
-                const double a = As[kk + (lane >> 4)][wm + (lane & 15)];
-                const double b = Bs[kk + (lane >> 4)][wn + (lane & 15)];
-                acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+            for (int u = 0; u < 4; ++u) {
+                const size_t kk = (size_t)(k0 + 4 * u + lk);
+                a[u] = aok ? pa[kk * sa] : 0.0;
+                b[u] = bok ? pb[kk * sb] : 0.0;
             }
-            __syncthreads();
+#pragma unroll
+            for (int u = 0; u < 4; ++u) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u], alpha * b[u], acc, 0, 0, 0);
+        }
+        for (; k0 < k; k0 += 4) {
+            const int kk = k0 + lk;
+            const double a = (aok && kk < k) ? pa[(size_t)kk * sa] : 0.0;
+            const double b = (bok && kk < k) ? pb[(size_t)kk * sb] : 0.0;
+            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, alpha * b, acc, 0, 0, 0);
         }
     }
     // accumulator register e of a lane holds D[lane / 16 + 4 e][lane % 16]
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
-        const int gi = row0 + wm + (lane >> 4) + 4 * e;
-        const int gj = col0 + wn + (lane & 15);
+        const int gi = row0 + lk + 4 * e, gj = col0 + li;
         if (gi < g.m && gj < g.n) {
             double* c = g.C + (size_t)gi * g.ldc + gj;
             *c = g.accumulate ? *c + acc[e] : acc[e];
@@ -836,7 +830,7 @@ void gemm_grouped(const GemmGroup* groups, int ngroups, const GemmTerm* terms, i
                   double bytes) {
     if (ntiles <= 0) return;
     Prof p(K_GEMM, flops, bytes);
-    hipLaunchKernelGGL(k_gemm_grouped, dim3(ntiles), dim3(256), 0, g_stream, groups, ngroups, terms);
+    hipLaunchKernelGGL(k_gemm_grouped, dim3((ntiles + 3) / 4), dim3(256), 0, g_stream, groups, ngroups, terms, ntiles);
     check(hipGetLastError(), "k_gemm_grouped");
 }
 void axpy_grouped(const AxpyGroup* groups, int ngroups, const AxpyTerm* terms, double flops, double bytes) {
