@@ -176,6 +176,7 @@ def main():
         "e2_after_4_sweeps": last["e2_sweep"][SWEEPS - 1] if len(last["e2_sweep"]) >= SWEEPS else None,
         "sweeps_done": last["n_sweeps_done"],
         "cg_iters": last["cg_iters"], "sigma_calls": last["sigma_calls"],
+        "work_lists_built": last["plan_builds"], "work_lists_replayed": last["plan_hits"],
         "host_phase_seconds": last["t_phase"],
         "kernel_seconds": {s["kernel"]: s["seconds"] for s in stats.values()},
         "roofline": {

@@ -122,6 +122,9 @@ typedef struct {
     int32_t flags;          /* bit 0: some local CG hit cg_max_iter (value still an upper bound) */
     double t_phase[6];      /* host seconds: two-site operators, work-list builds, local solves
                                (with device waits), truncation, environment updates, next guess */
+    int64_t plan_builds;    /* work lists built for this call (environment updates, sigma, right-hand
+                             * side, diagonal) */
+    int64_t plan_hits;      /* work lists replayed because the block layouts were unchanged */
 } mpspt_result;
 
 /* Run the sweep.  Errors: MPSPT_E_STATE if integrals, partition, Psi0 or the

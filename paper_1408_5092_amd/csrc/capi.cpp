@@ -226,6 +226,8 @@ mpspt_status mpspt_sweep(mpspt_ctx* ctx, const mpspt_sweep_params* params, mpspt
         out->t_total_s = r.t_total;
         out->flags = r.flags;
         for (int k = 0; k < 6; ++k) out->t_phase[k] = r.t_phase[k];
+        out->plan_builds = r.plan_builds;
+        out->plan_hits = r.plan_hits;
     });
 }
 

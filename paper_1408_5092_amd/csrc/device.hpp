@@ -13,50 +13,62 @@
 namespace mpspt {
 namespace dev {
 
+// Work lists address device memory as (slot, offset): the launch passes the
+// base pointer of each slot, so a list built once stays valid when the
+// buffers it reads and writes move.  Slot kAbsSlot has base 0 (the offset is
+// the address itself).
+constexpr int kSlots = 8;
+constexpr int kAbsSlot = kSlots - 1;
+struct Bases {
+    double* p[kSlots];
+};
+
 // C (m x n, leading dimension ldc) [+]= sum_t alpha_t op(A_t) op(B_t), computed in
 // GEMM_TILE x GEMM_TILE output tiles
 constexpr int GEMM_TILE = 16;
 struct GemmTerm {
-    const double* A;
-    const double* B;
+    int64_t oa, ob;
     double alpha;
     int32_t lda, ldb, k;
-    int32_t transA, transB;  // op(A) = A^T when set (A stored k x m)
+    int8_t sa, sb;
+    int8_t transA, transB;  // op(A) = A^T when set (A stored k x m)
 };
 struct GemmGroup {
-    double* C;
+    int64_t oc;
     int32_t ldc, m, n;
     int32_t term0, nterms;
-    int32_t accumulate;  // 0: overwrite C, 1: add to C
-    int32_t tile0;       // first tile index of this group in the launch
+    int32_t tile0;  // first tile index of this group in the launch
+    int8_t sc;
+    int8_t accumulate;  // 0: overwrite C, 1: add to C
 };
 
 // dst (m x n) [+]= sum_t alpha_t op(src_t)
 struct AxpyTerm {
-    const double* src;
-    int32_t lds, trans;
+    int64_t os;
     double alpha;
+    int32_t lds;
+    int8_t ss, trans;
 };
 struct AxpyGroup {
-    double* dst;
+    int64_t od;
     int32_t ldd, m, n;
     int32_t term0, nterms;
-    int32_t accumulate;
-    int32_t pad;
+    int8_t sd, accumulate;
 };
 
 // dst (m x n) = shift + sum_t c_t L_t[i * ls] R_t[j * rs]
 struct DiagTerm {
-    const double* L;
-    const double* R;
-    int32_t ls, rs;
+    int64_t ol, orr;
     double c;
+    int32_t ls, rs;
+    int8_t sl, sr;
 };
 struct DiagGroup {
-    double* dst;
+    int64_t od;
+    double shift;
     int32_t ldd, m, n;
     int32_t term0, nterms;
-    double shift;
+    int8_t sd;
 };
 
 // Symmetric eigenproblem of a density-matrix sector.  eig_reduce: A (n x n,
@@ -90,9 +102,9 @@ void sync();
 double now();  // host seconds
 
 // flops / bytes: algorithmic work of the launch, used only by the profiler
-void gemm_grouped(const GemmGroup* groups, int ngroups, const GemmTerm* terms, int ntiles, double flops = 0,
-                  double bytes = 0);
-void axpy_grouped(const AxpyGroup* groups, int ngroups, const AxpyTerm* terms, double flops = 0,
+void gemm_grouped(const Bases& b, const GemmGroup* groups, int ngroups, const GemmTerm* terms, int ntiles,
+                  double flops = 0, double bytes = 0);
+void axpy_grouped(const Bases& b, const AxpyGroup* groups, int ngroups, const AxpyTerm* terms, double flops = 0,
                   double bytes = 0);
 
 // Per-kernel timing with HIP events recorded on the library's stream.
@@ -103,7 +115,7 @@ struct KernelStats {
 };
 void profile_enable(bool on);          // resets the counters
 KernelStats profile_stats(int kind);   // waits for outstanding launches
-void diag_grouped(const DiagGroup* groups, int ngroups, const DiagTerm* terms);
+void diag_grouped(const Bases& b, const DiagGroup* groups, int ngroups, const DiagTerm* terms);
 // nmax / kmax: largest n / k among the jobs.  Variant 0 of each kernel keeps
 // the matrix (eig_reduce) or the basis (eig_vectors) in LDS, variant 1 in
 // global memory; batch jobs of one class together.  eig_vectors adds one to

@@ -153,6 +153,73 @@ void Env::index() {
         }
 }
 
+void Env::copy_layout(const Env& o) {
+    nch = o.nch;
+    bra = o.bra;
+    ket = o.ket;
+    blk = o.blk;
+    idx = o.idx;
+    by_w = o.by_w;
+    by_ib = o.by_ib;
+    dq = o.dq;
+    size = o.size;
+}
+
+namespace {
+// every field separately: equal signatures mean equal layouts
+void sig_bond(Sig& g, const Bond& b) {
+    g.add((int64_t)b.q.size());
+    for (size_t k = 0; k < b.q.size(); ++k) {
+        g.add(b.q[k].n);
+        g.add(b.q[k].s);
+        g.add(b.d[k]);
+    }
+}
+void sig_env(Sig& g, const Env& e) {
+    g.add(e.nch);
+    sig_bond(g, e.bra);
+    sig_bond(g, e.ket);
+    g.add((int64_t)e.blk.size());
+    for (const auto& b : e.blk) {
+        g.add(b.w);
+        g.add(b.ib);
+        g.add(b.ik);
+        g.add((int64_t)b.off);
+    }
+}
+void sig_site(Sig& g, const Site& a) {
+    sig_bond(g, a.L);
+    sig_bond(g, a.R);
+    g.add((int64_t)a.blk.size());
+    for (const auto& b : a.blk) {
+        g.add(b.il);
+        g.add(b.s);
+        g.add(b.jr);
+        g.add(b.col);
+    }
+    for (size_t k = 0; k < a.po.size(); ++k) {
+        g.add((int64_t)a.po[k]);
+        g.add(a.pw[k]);
+    }
+}
+void sig_two(Sig& g, const Two& a) {
+    sig_bond(g, a.L);
+    sig_bond(g, a.R);
+    g.add((int64_t)a.blk.size());
+    for (const auto& b : a.blk) {
+        g.add(b.il);
+        g.add(b.s1);
+        g.add(b.s2);
+        g.add(b.jr);
+        g.add(b.col);
+    }
+    for (size_t k = 0; k < a.po.size(); ++k) {
+        g.add((int64_t)a.po[k]);
+        g.add(a.pw[k]);
+    }
+}
+}  // namespace
+
 TwoOp make_twoop(const MPO& m, int i) {
     TwoOp O;
     O.nin = m.dims[i];
@@ -190,12 +257,37 @@ TwoOp make_twoop(const MPO& m, int i) {
 }
 
 // ---------------------------------------------------------- work lists
+void SlotMap::ref(const double* p, int8_t& slot, int64_t& off) const {
+    for (int k = 0; k < dev::kAbsSlot; ++k)
+        if (base_[k] && p >= base_[k] && p < base_[k] + cnt_[k]) {
+            slot = (int8_t)k;
+            off = p - base_[k];
+            return;
+        }
+    slot = (int8_t)dev::kAbsSlot;
+    off = (int64_t)(reinterpret_cast<uintptr_t>(p) / sizeof(double));
+}
+dev::Bases SlotMap::bases() const {
+    dev::Bases b;
+    for (int k = 0; k < dev::kSlots; ++k) b.p[k] = const_cast<double*>(base_[k]);
+    b.p[dev::kAbsSlot] = nullptr;
+    return b;
+}
+
 void GemmBatch::group(double* C, int ldc, int m, int n, bool acc) {
+    dev::GemmGroup g{};
+    g.term0 = (int)t_.size();
     if (m <= 0 || n <= 0) {
-        g_.push_back({nullptr, 0, 0, 0, (int)t_.size(), 0, 1, -1});  // placeholder, dropped
+        g.tile0 = -1;  // placeholder, dropped
+        g_.push_back(g);
         return;
     }
-    dev::GemmGroup g{C, ldc, m, n, (int)t_.size(), 0, acc ? 1 : 0, tiles_};
+    slots_.ref(C, g.sc, g.oc);
+    g.ldc = ldc;
+    g.m = m;
+    g.n = n;
+    g.accumulate = acc ? 1 : 0;
+    g.tile0 = tiles_;
     tiles_ += ((m + kTile - 1) / kTile) * ((n + kTile - 1) / kTile);
     g_.push_back(g);
     bytes_ += 8.0 * m * n * (acc ? 2 : 1);
@@ -203,15 +295,24 @@ void GemmBatch::group(double* C, int ldc, int m, int n, bool acc) {
 void GemmBatch::term(const double* A, int lda, bool tA, const double* B, int ldb, bool tB, int k, double alpha) {
     dev::GemmGroup& g = g_.back();
     if (g.tile0 < 0 || k <= 0 || alpha == 0.0) return;
-    t_.push_back({A, B, alpha, lda, ldb, k, tA ? 1 : 0, tB ? 1 : 0});
+    dev::GemmTerm t{};
+    slots_.ref(A, t.sa, t.oa);
+    slots_.ref(B, t.sb, t.ob);
+    t.alpha = alpha;
+    t.lda = lda;
+    t.ldb = ldb;
+    t.k = k;
+    t.transA = tA ? 1 : 0;
+    t.transB = tB ? 1 : 0;
+    t_.push_back(t);
     ++g.nterms;
     flops_ += 2.0 * g.m * g.n * k;
     bytes_ += 8.0 * ((double)g.m * k + (double)k * g.n);
 }
 // Groups whose summed k is long compared with the launch's work are split
 // into segments (at term boundaries, or inside a long term) that write
-// partial products to scratch; a grouped axpy then adds the segments into C
-// in order, so the result stays deterministic.
+// partial products to the batch's scratch; a grouped axpy then adds the
+// segments into C in order, so the result stays deterministic.
 void GemmBatch::upload() {
     if (split_) {  // already laid out
         dg_.upload(g_);
@@ -221,6 +322,7 @@ void GemmBatch::upload() {
     }
     split_ = true;
     std::vector<dev::GemmGroup> live;
+    std::vector<long> ksum;
     live.reserve(g_.size());
     double work = 0;
     for (auto& g : g_) {
@@ -230,19 +332,16 @@ void GemmBatch::upload() {
         const int tl = ((g.m + kTile - 1) / kTile) * ((g.n + kTile - 1) / kTile);
         work += (double)tl * K;
         live.push_back(g);
+        ksum.push_back(K);
     }
     const long kseg = std::max<long>(512, (long)(work / 8192.0));
     size_t psz = 0;
     std::vector<int> nseg(live.size(), 1);
-    for (size_t gi = 0; gi < live.size(); ++gi) {
-        const auto& g = live[gi];
-        long K = 0;
-        for (int t = 0; t < g.nterms; ++t) K += t_[g.term0 + t].k;
-        if (K > kseg) {
-            nseg[gi] = (int)((K + kseg - 1) / kseg);
-            psz += (size_t)nseg[gi] * g.m * g.n;
+    for (size_t gi = 0; gi < live.size(); ++gi)
+        if (ksum[gi] > kseg) {
+            nseg[gi] = (int)((ksum[gi] + kseg - 1) / kseg);
+            psz += (size_t)nseg[gi] * live[gi].m * live[gi].n;
         }
-    }
     part_.ensure(std::max<size_t>(psz, 1));
     red_.clear();
     std::vector<dev::GemmGroup> gs;
@@ -250,7 +349,7 @@ void GemmBatch::upload() {
     gs.reserve(live.size());
     ts.reserve(t_.size());
     int tiles = 0;
-    size_t poff = 0;
+    int64_t poff = 0;
     for (size_t gi = 0; gi < live.size(); ++gi) {
         const auto& g = live[gi];
         const int tl = ((g.m + kTile - 1) / kTile) * ((g.n + kTile - 1) / kTile);
@@ -263,29 +362,38 @@ void GemmBatch::upload() {
             gs.push_back(c);
             continue;
         }
-        long K = 0;
-        for (int t = 0; t < g.nterms; ++t) K += t_[g.term0 + t].k;
-        const long per = (K + nseg[gi] - 1) / nseg[gi];
-        red_.group(g.C, g.ldc, g.m, g.n, g.accumulate != 0);
-        dev::GemmGroup cur{part_.p + poff, g.n, g.m, g.n, (int)ts.size(), 0, 0, tiles};
+        const long per = (ksum[gi] + nseg[gi] - 1) / nseg[gi];
+        red_.group_ref(g.sc, g.oc, g.ldc, g.m, g.n, g.accumulate != 0);
+        auto fresh = [&]() {
+            dev::GemmGroup c{};
+            c.sc = (int8_t)kPartSlot;
+            c.oc = poff;
+            c.ldc = g.n;
+            c.m = g.m;
+            c.n = g.n;
+            c.term0 = (int)ts.size();
+            c.tile0 = tiles;
+            return c;
+        };
+        dev::GemmGroup cur = fresh();
         long used = 0;
         auto close = [&]() {
             if (cur.nterms == 0) return;
             gs.push_back(cur);
             tiles += tl;
-            red_.term(cur.C, g.n, false, 1.0);
-            poff += (size_t)g.m * g.n;
-            cur = dev::GemmGroup{part_.p + poff, g.n, g.m, g.n, (int)ts.size(), 0, 0, tiles};
+            red_.term_ref((int8_t)kPartSlot, cur.oc, g.n, false, 1.0);
+            poff += (int64_t)g.m * g.n;
+            cur = fresh();
             used = 0;
         };
         for (int t = 0; t < g.nterms; ++t) {
-            dev::GemmTerm tm = t_[g.term0 + t];
+            const dev::GemmTerm tm = t_[g.term0 + t];
             int k0 = 0;
             while (k0 < tm.k) {
                 const int take = (int)std::min<long>(tm.k - k0, per - used);
                 dev::GemmTerm sub = tm;
-                sub.A = tm.A + (size_t)k0 * (tm.transA ? (size_t)tm.lda : 1);
-                sub.B = tm.B + (size_t)k0 * (tm.transB ? 1 : (size_t)tm.ldb);
+                sub.oa = tm.oa + (int64_t)k0 * (tm.transA ? tm.lda : 1);
+                sub.ob = tm.ob + (int64_t)k0 * (tm.transB ? 1 : tm.ldb);
                 sub.k = take;
                 ts.push_back(sub);
                 ++cur.nterms;
@@ -304,17 +412,45 @@ void GemmBatch::upload() {
     red_.upload();
 }
 void GemmBatch::run() const {
-    if (tiles_ > 0) dev::gemm_grouped(dg_.p, (int)g_.size(), dt_.p, tiles_, flops_, bytes_);
-    red_.run();
+    dev::Bases b = slots_.bases();
+    b.p[kPartSlot] = part_.p;
+    if (tiles_ > 0) dev::gemm_grouped(b, dg_.p, (int)g_.size(), dt_.p, tiles_, flops_, bytes_);
+    red_.run(b);
 }
 
 void AxpyBatch::group(double* dst, int ldd, int m, int n, bool acc) {
-    g_.push_back({dst, ldd, m, n, (int)t_.size(), 0, acc ? 1 : 0, 0});
+    int8_t sl;
+    int64_t off;
+    slots_.ref(dst, sl, off);
+    group_ref(sl, off, ldd, m, n, acc);
+}
+void AxpyBatch::group_ref(int8_t slot, int64_t off, int ldd, int m, int n, bool acc) {
+    dev::AxpyGroup g{};
+    g.sd = slot;
+    g.od = off;
+    g.ldd = ldd;
+    g.m = m;
+    g.n = n;
+    g.term0 = (int)t_.size();
+    g.accumulate = acc ? 1 : 0;
+    g_.push_back(g);
     if (m > 0 && n > 0) bytes_ += 8.0 * m * n * (acc ? 2 : 1);
 }
 void AxpyBatch::term(const double* src, int lds, bool trans, double alpha) {
+    int8_t sl;
+    int64_t off;
+    slots_.ref(src, sl, off);
+    term_ref(sl, off, lds, trans, alpha);
+}
+void AxpyBatch::term_ref(int8_t slot, int64_t off, int lds, bool trans, double alpha) {
     dev::AxpyGroup& g = g_.back();
-    t_.push_back({src, lds, trans ? 1 : 0, alpha});
+    dev::AxpyTerm t{};
+    t.ss = slot;
+    t.os = off;
+    t.lds = lds;
+    t.trans = trans ? 1 : 0;
+    t.alpha = alpha;
+    t_.push_back(t);
     ++g.nterms;
     flops_ += 2.0 * g.m * g.n;
     bytes_ += 8.0 * g.m * g.n;
@@ -327,8 +463,8 @@ void AxpyBatch::upload() {
     dg_.upload(g_);
     dt_.upload(t_);
 }
-void AxpyBatch::run() const {
-    if (!g_.empty()) dev::axpy_grouped(dg_.p, (int)g_.size(), dt_.p, flops_, bytes_);
+void AxpyBatch::run(const dev::Bases& b) const {
+    if (!g_.empty()) dev::axpy_grouped(b, dg_.p, (int)g_.size(), dt_.p, flops_, bytes_);
 }
 
 // ------------------------------------------------------------- inputs
@@ -350,10 +486,18 @@ void Engine::set_partition(std::vector<double> eps) {
     have_psi0 = have_psi1 = false;
 }
 
+void Engine::clear_plans() {
+    for (auto& v : eff_plans_) v.clear();
+    for (auto& v : env_plans_) v.clear();
+    diag_plans_.clear();
+}
+
 void Engine::build_mpos() {
+    clear_plans();
     mpo_h0_ = build_mpo(OpKind::H0, k_a_, k_v_, h_, eri_, eps_);
     mpo_v_ = build_mpo(OpKind::VPsi0, k_a_, k_v_, h_, eri_, eps_);
     twoop_cache_[0].clear();
+    clear_plans();
     twoop_cache_[1].clear();
 }
 
@@ -424,6 +568,7 @@ void Engine::set_psi0(int n_elec, int two_sz, const std::vector<Bond>& bonds,
                       const std::vector<std::vector<double>>& sites) {
     if (!have_part) throw err(MPSPT_E_STATE, "load integrals and the H0 partition before Psi0");
     if ((int)bonds.size() != k_a_ + 1 || (int)sites.size() != k_a_) throw err(MPSPT_E_ARG, "Psi0 needs k_a sites");
+    clear_plans();
     if (bonds[0].q.size() != 1 || bonds[0].q[0] != QN{0, 0} || bonds[0].d[0] != 1)
         throw err(MPSPT_E_QN, "first bond of Psi0 must be the single label (0, 0)");
     if (bonds[k_a_].q.size() != 1 || bonds[k_a_].q[0] != QN{n_elec, two_sz} || bonds[k_a_].d[0] != 1)
@@ -534,11 +679,49 @@ void Engine::contract_sites(const Site& A, const Site& B, const Two& lay, double
     g.run();
 }
 
-void Engine::env_left(Env& out, const Env& L, const Site& Abra, const Site& Aket, const MPO& m, int i) {
+void Engine::bind_env(GemmBatch& g, const Env& in, const Site& Abra, const Site& Aket, size_t tsz, const Env& out) {
+    g.bind(0, in.data.p, in.size);
+    g.bind(1, Abra.data.p, Abra.size);
+    g.bind(2, Aket.data.p, Aket.size);
+    g.bind(3, T_.p, tsz);
+    g.bind(4, out.data.p, out.size);
+}
+
+// Replays a cached environment update when its input layouts are unchanged.
+bool Engine::env_cached(Env& out, const Env& in, const Site& Abra, const Site& Aket, const MPO& m, int i,
+                        std::unique_ptr<EnvPlan>* plan, Sig& sig) {
+    if (!plan) return false;
+    sig.add((int64_t)(uintptr_t)&m);
+    sig.add(i);
+    sig_env(sig, in);
+    sig_site(sig, Abra);
+    sig_site(sig, Aket);
+    if (!*plan || (*plan)->sig != sig) return false;
+    EnvPlan& P = **plan;
+    out.copy_layout(P.lay);
+    out.data.ensure(std::max<size_t>(out.size, 1));
+    T_.ensure(std::max<size_t>(P.tsz, 1));
+    bind_env(P.ga, in, Abra, Aket, P.tsz, out);
+    bind_env(P.gb, in, Abra, Aket, P.tsz, out);
+    P.ga.run();
+    P.gb.run();
+    ++res_.plan_hits;
+    return true;
+}
+
+void Engine::env_left(Env& out, const Env& L, const Site& Abra, const Site& Aket, const MPO& m, int i,
+                      std::unique_ptr<EnvPlan>* plan) {
+    Sig sig;
+    if (env_cached(out, L, Abra, Aket, m, i, plan, sig)) return;
+    DevBuf keep = std::move(out.data);
     out = Env();
+    out.data = std::move(keep);
     out.nch = m.dims[i + 1];
     out.bra = Abra.R;
     out.ket = Aket.R;
+    auto fresh = std::make_unique<EnvPlan>();
+    GemmBatch& ga = fresh->ga;
+    GemmBatch& gb = fresh->gb;
     // stage a: T[lb] = L block . row panel of Aket
     std::vector<size_t> toff(L.blk.size(), (size_t)-1);
     size_t tsz = 0;
@@ -549,7 +732,7 @@ void Engine::env_left(Env& out, const Env& L, const Site& Abra, const Site& Aket
         tsz += (size_t)L.blk[lb].rows * Aket.pw[ik];
     }
     T_.ensure(std::max<size_t>(tsz, 1));
-    GemmBatch ga;
+    bind_env(ga, L, Abra, Aket, tsz, out);
     for (size_t lb = 0; lb < L.blk.size(); ++lb) {
         if (toff[lb] == (size_t)-1) continue;
         const auto& B = L.blk[lb];
@@ -583,8 +766,8 @@ void Engine::env_left(Env& out, const Env& L, const Site& Abra, const Site& Aket
     out.size = off;
     out.dq = m.dq[i + 1];
     out.index();
-    out.data.alloc(std::max<size_t>(off, 1));
-    GemmBatch gb;
+    out.data.ensure(std::max<size_t>(off, 1));
+    bind_env(gb, L, Abra, Aket, tsz, out);
     size_t bi = 0;
     outs.each([&](int, int, int, const std::vector<Tm>& terms) {
         const auto& B = out.blk[bi++];
@@ -595,13 +778,28 @@ void Engine::env_left(Env& out, const Env& L, const Site& Abra, const Site& Aket
     gb.upload();
     ga.run();
     gb.run();
+    if (plan) {
+        fresh->sig = std::move(sig);
+        fresh->lay.copy_layout(out);
+        fresh->tsz = tsz;
+        *plan = std::move(fresh);
+        ++res_.plan_builds;
+    }
 }
 
-void Engine::env_right(Env& out, const Env& R, const Site& Abra, const Site& Aket, const MPO& m, int i) {
+void Engine::env_right(Env& out, const Env& R, const Site& Abra, const Site& Aket, const MPO& m, int i,
+                       std::unique_ptr<EnvPlan>* plan) {
+    Sig sig;
+    if (env_cached(out, R, Abra, Aket, m, i, plan, sig)) return;
+    DevBuf keep = std::move(out.data);
     out = Env();
+    out.data = std::move(keep);
     out.nch = m.dims[i];
     out.bra = Abra.L;
     out.ket = Aket.L;
+    auto fresh = std::make_unique<EnvPlan>();
+    GemmBatch& ga = fresh->ga;
+    GemmBatch& gb = fresh->gb;
     struct Tm { const double* A; int lda; size_t toff; int ldb; int k; double a; };
     // T(rb, t) = R block rb . (Aket block with right sector ib_ket(rb) and local state t)^T;
     // for a fixed R block and local state that Aket block is unique
@@ -635,7 +833,7 @@ void Engine::env_right(Env& out, const Env& R, const Site& Abra, const Site& Ake
             }
     }
     T_.ensure(std::max<size_t>(tsz, 1));
-    GemmBatch ga;
+    bind_env(ga, R, Abra, Aket, tsz, out);
     for (const Ta& t : tlist) {
         const auto& B = R.blk[t.rb];
         const auto& K = Aket.blk[t.ak];
@@ -650,8 +848,8 @@ void Engine::env_right(Env& out, const Env& R, const Site& Abra, const Site& Ake
     out.size = off;
     out.dq = m.dq[i];
     out.index();
-    out.data.alloc(std::max<size_t>(off, 1));
-    GemmBatch gb;
+    out.data.ensure(std::max<size_t>(off, 1));
+    bind_env(gb, R, Abra, Aket, tsz, out);
     size_t bi = 0;
     outs.each([&](int, int, int, const std::vector<Tm>& terms) {
         const auto& B = out.blk[bi++];
@@ -662,6 +860,13 @@ void Engine::env_right(Env& out, const Env& R, const Site& Abra, const Site& Ake
     gb.upload();
     ga.run();
     gb.run();
+    if (plan) {
+        fresh->sig = std::move(sig);
+        fresh->lay.copy_layout(out);
+        fresh->tsz = tsz;
+        *plan = std::move(fresh);
+        ++res_.plan_builds;
+    }
 }
 
 void Engine::build_effop(EffOp& op, const Env& L, const Env& R, const TwoOp& O, const Two& ket,
@@ -670,6 +875,10 @@ void Engine::build_effop(EffOp& op, const Env& L, const Env& R, const TwoOp& O, 
     op.st2.clear();
     op.st3.clear();
     op.flops = op.bytes = 0;
+    op.bind(0, L.data.p, L.size);
+    op.bind(1, R.data.p, R.size);
+    op.bind(2, xket, ket.size);
+    op.bind(3, ybra, bra.size);
     // stage 1 layout: U[lb] = L block . ket row panel
     std::vector<size_t> uoff(L.blk.size(), (size_t)-1);
     size_t usz = 0;
@@ -712,6 +921,8 @@ void Engine::build_effop(EffOp& op, const Env& L, const Env& R, const TwoOp& O, 
     }
     op.U.ensure(std::max<size_t>(usz, 1));
     op.V.ensure(std::max<size_t>(vsz, 1));
+    op.bind(4, op.U.p, usz);
+    op.bind(5, op.V.p, vsz);
     for (size_t lb = 0; lb < L.blk.size(); ++lb) {
         if (uoff[lb] == (size_t)-1 || !lused[lb]) continue;
         const auto& B = L.blk[lb];
@@ -742,32 +953,98 @@ void Engine::build_effop(EffOp& op, const Env& L, const Env& R, const TwoOp& O, 
     op.flops = op.st1.flops() + op.st2.flops() + op.st3.flops();
 }
 
-void Engine::build_diag(const Env& L, const Env& R, const TwoOp& O, const Two& lay, double* d, double shift) {
-    std::vector<dev::DiagGroup> gs;
-    std::vector<dev::DiagTerm> ts;
-    for (size_t bb = 0; bb < lay.blk.size(); ++bb) {
-        const auto& Y = lay.blk[bb];
-        dev::DiagGroup g{d + lay.off((int)bb), lay.ld((int)bb), Y.rows, Y.cols, (int)ts.size(), 0, shift};
-        for (int rb : R.by_ib[Y.jr]) {
-            const int wp = R.blk[rb].w;
-            if (R.blk[rb].ik != Y.jr) continue;
-            for (const auto& t : O.by_out[(size_t)wp * 16 + Y.s1 * 4 + Y.s2]) {
-                if (t.s1 != Y.s1 || t.s2 != Y.s2) continue;
-                int lb = L.find(t.w, Y.il);
-                if (lb < 0 || L.blk[lb].ik != Y.il) continue;
-                ts.push_back({L.data.p + L.blk[lb].off, R.data.p + R.blk[rb].off, L.blk[lb].cols + 1,
-                              R.blk[rb].cols + 1, t.v});
-                ++g.nterms;
-            }
-        }
-        if (Y.rows > 0 && Y.cols > 0) gs.push_back(g);
+// The effective operator of window i in role r (0: H0 - E0 on the two-site
+// space, 1: the right-hand side from Psi0), rebuilt only when its layouts
+// changed since the last sweep.
+EffOp& Engine::effop(int r, int i, const Env& L, const Env& R, const TwoOp& O, const Two& ket, const double* xket,
+                     const Two& bra, double* ybra) {
+    auto& plans = eff_plans_[r];
+    if ((int)plans.size() <= i) plans.resize(i + 1);
+    Sig sig;
+    sig.add((int64_t)(uintptr_t)&O);
+    sig_env(sig, L);
+    sig_env(sig, R);
+    sig_two(sig, ket);
+    sig_two(sig, bra);
+    auto& pl = plans[i];
+    if (!pl || pl->sig != sig) {
+        pl = std::make_unique<EffPlan>();
+        build_effop(pl->op, L, R, O, ket, xket, bra, ybra);
+        pl->sig = std::move(sig);
+        ++res_.plan_builds;
+    } else {
+        EffOp& op = pl->op;
+        op.bind(0, L.data.p, L.size);
+        op.bind(1, R.data.p, R.size);
+        op.bind(2, xket, ket.size);
+        op.bind(3, ybra, bra.size);
+        op.bind(4, op.U.p, op.U.n);
+        op.bind(5, op.V.p, op.V.n);
+        ++res_.plan_hits;
     }
-    DevArr<dev::DiagGroup> dg;
-    DevArr<dev::DiagTerm> dt;
-    dg.upload(gs);
-    dt.upload(ts);
-    if (!gs.empty()) dev::diag_grouped(dg.p, (int)gs.size(), dt.p);
-    dev::sync();
+    return pl->op;
+}
+
+void Engine::build_diag(int i, const Env& L, const Env& R, const TwoOp& O, const Two& lay, double* d, double shift) {
+    if ((int)diag_plans_.size() <= i) diag_plans_.resize(i + 1);
+    Sig sig;
+    sig.add((int64_t)(uintptr_t)&O);
+    int64_t sbits;
+    std::memcpy(&sbits, &shift, sizeof(sbits));
+    sig.add(sbits);
+    sig_env(sig, L);
+    sig_env(sig, R);
+    sig_two(sig, lay);
+    auto& pl = diag_plans_[i];
+    if (!pl || pl->sig != sig) {
+        pl = std::make_unique<DiagPlan>();
+        SlotMap sm;
+        sm.bind(0, L.data.p, L.size);
+        sm.bind(1, R.data.p, R.size);
+        sm.bind(2, d, lay.size);
+        std::vector<dev::DiagGroup> gs;
+        std::vector<dev::DiagTerm> ts;
+        for (size_t bb = 0; bb < lay.blk.size(); ++bb) {
+            const auto& Y = lay.blk[bb];
+            dev::DiagGroup g{};
+            sm.ref(d + lay.off((int)bb), g.sd, g.od);
+            g.shift = shift;
+            g.ldd = lay.ld((int)bb);
+            g.m = Y.rows;
+            g.n = Y.cols;
+            g.term0 = (int)ts.size();
+            for (int rb : R.by_ib[Y.jr]) {
+                const int wp = R.blk[rb].w;
+                if (R.blk[rb].ik != Y.jr) continue;
+                for (const auto& t : O.by_out[(size_t)wp * 16 + Y.s1 * 4 + Y.s2]) {
+                    if (t.s1 != Y.s1 || t.s2 != Y.s2) continue;
+                    int lb = L.find(t.w, Y.il);
+                    if (lb < 0 || L.blk[lb].ik != Y.il) continue;
+                    dev::DiagTerm dt{};
+                    sm.ref(L.data.p + L.blk[lb].off, dt.sl, dt.ol);
+                    sm.ref(R.data.p + R.blk[rb].off, dt.sr, dt.orr);
+                    dt.ls = L.blk[lb].cols + 1;
+                    dt.rs = R.blk[rb].cols + 1;
+                    dt.c = t.v;
+                    ts.push_back(dt);
+                    ++g.nterms;
+                }
+            }
+            if (Y.rows > 0 && Y.cols > 0) gs.push_back(g);
+        }
+        pl->ng = (int)gs.size();
+        pl->dg.upload(gs);
+        pl->dt.upload(ts);
+        pl->sig = std::move(sig);
+        ++res_.plan_builds;
+    } else {
+        ++res_.plan_hits;
+    }
+    SlotMap sm;
+    sm.bind(0, L.data.p, L.size);
+    sm.bind(1, R.data.p, R.size);
+    sm.bind(2, d, lay.size);
+    if (pl->ng > 0) dev::diag_grouped(sm.bases(), pl->dg.p, pl->ng, pl->dt.p);
 }
 
 // ----------------------------------------------------------- truncation
@@ -1013,13 +1290,15 @@ double Engine::truncate(int i, bool forward, const Two& lay, const double* x, in
 }
 
 void Engine::upd_left(int i) {
-    env_left(LH_[i + 1], LH_[i], A_[i], A_[i], mpo_h0_, i);
-    if (!gs_) env_left(LV_[i + 1], LV_[i], A_[i], P0_[i], mpo_v_, i);
+    if ((int)env_plans_[0].size() < n_) for (auto& v : env_plans_) v.resize(n_);
+    env_left(LH_[i + 1], LH_[i], A_[i], A_[i], mpo_h0_, i, &env_plans_[0][i]);
+    if (!gs_) env_left(LV_[i + 1], LV_[i], A_[i], P0_[i], mpo_v_, i, &env_plans_[1][i]);
 }
 
 void Engine::upd_right(int i) {
-    env_right(RH_[i], RH_[i + 1], A_[i], A_[i], mpo_h0_, i);
-    if (!gs_) env_right(RV_[i], RV_[i + 1], A_[i], P0_[i], mpo_v_, i);
+    if ((int)env_plans_[0].size() < n_) for (auto& v : env_plans_) v.resize(n_);
+    env_right(RH_[i], RH_[i + 1], A_[i], A_[i], mpo_h0_, i, &env_plans_[2][i]);
+    if (!gs_) env_right(RV_[i], RV_[i + 1], A_[i], P0_[i], mpo_v_, i, &env_plans_[3][i]);
 }
 
 // ---------------------------------------------------------- local solve
@@ -1034,12 +1313,9 @@ int Engine::solve(int i, double& e2) {
     const TwoOp& Ov = twoop(1, i);
     res_.t_phase[0] += dev::now() - t;
     t = dev::now();
-    EffOp rhs;
-    build_effop(rhs, LV_[i], RV_[i + 2], Ov, P0x_lay_[i], P0x_[i].p, lay, b_.p);
-    rhs.run();
-    build_diag(LH_[i], RH_[i + 2], O, lay, d_.p, -E0_);
-    EffOp sig;
-    build_effop(sig, LH_[i], RH_[i + 2], O, lay, p_.p, lay, q_.p);
+    effop(1, i, LV_[i], RV_[i + 2], Ov, P0x_lay_[i], P0x_[i].p, lay, b_.p).run();
+    build_diag(i, LH_[i], RH_[i + 2], O, lay, d_.p, -E0_);
+    const EffOp& sig = effop(0, i, LH_[i], RH_[i + 2], O, lay, p_.p, lay, q_.p);
     res_.t_phase[1] += dev::now() - t;
     t = dev::now();
     struct PhaseTimer {
@@ -1279,6 +1555,7 @@ double Engine::ground_state(int n_elec, int two_sz, const std::vector<Bond>& bon
     n_ = k_a_;
     mpo_h0_ = build_mpo(OpKind::HAct, k_a_, k_v_, h_, eri_, eps_);
     twoop_cache_[0].clear();
+    clear_plans();
     adm_ = adm;
     res_ = SweepResult();
     trace_.clear();
@@ -1303,6 +1580,8 @@ double Engine::ground_state(int n_elec, int two_sz, const std::vector<Bond>& bon
         n_ = n_save;
         mpo_h0_ = std::move(h0_save);
         twoop_cache_[0].clear();
+        clear_plans();
+    clear_plans();
         adm_ = std::move(adm_save);
         A_.clear();
         throw;
@@ -1311,6 +1590,7 @@ double Engine::ground_state(int n_elec, int two_sz, const std::vector<Bond>& bon
     n_ = n_save;
     mpo_h0_ = std::move(h0_save);
     twoop_cache_[0].clear();
+    clear_plans();
     adm_ = std::move(adm_save);
     A_.clear();
     gs_trace_ = trace_;
@@ -1330,9 +1610,8 @@ int Engine::davidson(int i, double& e) {
     partials_.ensure(dev::kPartials);
     scal_.ensure(dev::S_N);
     const TwoOp& O = twoop(0, i);
-    build_diag(LH_[i], RH_[i + 2], O, lay, d_.p, 0.0);
-    EffOp sig;
-    build_effop(sig, LH_[i], RH_[i + 2], O, lay, p_.p, lay, q_.p);
+    build_diag(i, LH_[i], RH_[i + 2], O, lay, d_.p, 0.0);
+    const EffOp& sig = effop(0, i, LH_[i], RH_[i + 2], O, lay, p_.p, lay, q_.p);
     double sc[dev::S_N];
     auto dotp = [&](const double* a, const double* b) {
         dev::dot(a, b, n, scal_.p, dev::S_DOT, partials_.p);

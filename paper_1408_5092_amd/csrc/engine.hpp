@@ -107,6 +107,7 @@ struct Env {
     DevBuf data;
     int find(int w, int ib) const { return idx[(size_t)w * bra.q.size() + ib]; }
     void index();
+    void copy_layout(const Env& o);  // everything but the data
 };
 
 // Two-site operator of a window: sum over the middle channel of W_i (x) W_{i+1}.
@@ -117,19 +118,43 @@ struct TwoOp {
 };
 TwoOp make_twoop(const MPO& m, int i);
 
+// Slots of a work list: the device buffers it addresses, each as a base
+// pointer and an extent in doubles.  Pointers handed to group()/term() are
+// stored relative to the slot that contains them (the absolute slot when
+// none does); rebinding a slot moves every reference to it.
+class SlotMap {
+  public:
+    void bind(int slot, const double* base, size_t count) {
+        base_[slot] = base;
+        cnt_[slot] = count;
+    }
+    void ref(const double* p, int8_t& slot, int64_t& off) const;
+    dev::Bases bases() const;
+
+  private:
+    const double* base_[dev::kSlots] = {};
+    size_t cnt_[dev::kSlots] = {};
+};
+
 // Work list of grouped block axpys, reusable across launches.
 class AxpyBatch {
   public:
     void clear() { g_.clear(); t_.clear(); flops_ = 0; bytes_ = 0; }
+    void bind(int slot, const double* base, size_t count) { slots_.bind(slot, base, count); }
     void group(double* dst, int ldd, int m, int n, bool acc);
     void term(const double* src, int lds, bool trans, double alpha);
+    // slot-relative forms
+    void group_ref(int8_t slot, int64_t off, int ldd, int m, int n, bool acc);
+    void term_ref(int8_t slot, int64_t off, int lds, bool trans, double alpha);
     void upload();
-    void run() const;
+    void run() const { run(slots_.bases()); }
+    void run(const dev::Bases& b) const;
     bool empty() const { return g_.empty(); }
     double flops() const { return flops_; }
     double bytes() const { return bytes_; }
 
   private:
+    SlotMap slots_;
     std::vector<dev::AxpyGroup> g_;
     std::vector<dev::AxpyTerm> t_;
     DevArr<dev::AxpyGroup> dg_;
@@ -137,10 +162,13 @@ class AxpyBatch {
     double flops_ = 0, bytes_ = 0;
 };
 
-// Work list of grouped GEMMs, reusable across launches.
+// Work list of grouped GEMMs, reusable across launches.  Slot kPartSlot is
+// the batch's own split-k scratch.
 class GemmBatch {
   public:
+    static constexpr int kPartSlot = dev::kAbsSlot - 1;
     void clear() { g_.clear(); t_.clear(); tiles_ = 0; flops_ = 0; bytes_ = 0; red_.clear(); split_ = false; }
+    void bind(int slot, const double* base, size_t count) { slots_.bind(slot, base, count); }
     void group(double* C, int ldc, int m, int n, bool acc);
     void term(const double* A, int lda, bool tA, const double* B, int ldb, bool tB, int k, double alpha);
     void upload();
@@ -151,6 +179,7 @@ class GemmBatch {
     size_t nterms() const { return t_.size(); }
 
   private:
+    SlotMap slots_;
     std::vector<dev::GemmGroup> g_;
     std::vector<dev::GemmTerm> t_;
     DevArr<dev::GemmGroup> dg_;
@@ -162,15 +191,29 @@ class GemmBatch {
     bool split_ = false;
 };
 
-
-// y = sum L (x) O (x) R applied to x (three grouped launches).
+// y = sum L (x) O (x) R applied to x (three grouped launches).  Slots:
+// 0 left environment, 1 right environment, 2 x, 3 y, 4 U, 5 V.
 struct EffOp {
     GemmBatch st1;
     AxpyBatch st2;
     GemmBatch st3;
     DevBuf U, V;
     double flops = 0, bytes = 0;
+    void bind(int slot, const double* base, size_t count) {
+        st1.bind(slot, base, count);
+        st2.bind(slot, base, count);
+        st3.bind(slot, base, count);
+    }
     void run() const { st1.run(); st2.run(); st3.run(); }
+};
+
+// Layout signature of the inputs a work list was built from; a cached list
+// is reused while the signature is unchanged.
+struct Sig {
+    std::vector<int64_t> v;
+    void add(int64_t x) { v.push_back(x); }
+    bool operator==(const Sig& o) const { return v == o.v; }
+    bool operator!=(const Sig& o) const { return v != o.v; }
 };
 
 struct StepRecord {
@@ -192,6 +235,7 @@ struct SweepResult {
     // solves (including waits on the device), truncation, environment updates,
     // next guess
     double t_phase[6] = {0, 0, 0, 0, 0, 0};
+    long long plan_builds = 0, plan_hits = 0;  // work lists built / replayed from the plan caches
 };
 
 class Engine {
@@ -247,15 +291,43 @@ class Engine {
     std::vector<StepRecord> gs_trace_;
 
     void build_mpos();
+    // cached work lists per window (layout signature + device lists)
+    struct EffPlan {
+        Sig sig;
+        EffOp op;
+    };
+    struct EnvPlan {
+        Sig sig;
+        Env lay;
+        GemmBatch ga, gb;
+        size_t tsz = 0;
+    };
+    struct DiagPlan {
+        Sig sig;
+        DevArr<dev::DiagGroup> dg;
+        DevArr<dev::DiagTerm> dt;
+        int ng = 0;
+    };
+    std::vector<std::unique_ptr<EffPlan>> eff_plans_[2];  // sigma, right-hand side
+    std::vector<std::unique_ptr<EnvPlan>> env_plans_[4];  // LH, LV, RH, RV updates
+    std::vector<std::unique_ptr<DiagPlan>> diag_plans_;
+    void clear_plans();
+    EffOp& effop(int r, int i, const Env& L, const Env& R, const TwoOp& O, const Two& ket, const double* xket,
+                 const Two& bra, double* ybra);
+    void bind_env(GemmBatch& g, const Env& in, const Site& Abra, const Site& Aket, size_t tsz, const Env& out);
+    bool env_cached(Env& out, const Env& in, const Site& Abra, const Site& Aket, const MPO& m, int i,
+                    std::unique_ptr<EnvPlan>* plan, Sig& sig);
     // two-site operators per window, built once per MPO (which = 0: H0, 1: V)
     std::vector<std::unique_ptr<TwoOp>> twoop_cache_[2];
     const TwoOp& twoop(int which, int i);
     Env trivial_env(const Bond& bra, const Bond& ket) const;
-    void env_left(Env& out, const Env& L, const Site& Abra, const Site& Aket, const MPO& m, int i);
-    void env_right(Env& out, const Env& R, const Site& Abra, const Site& Aket, const MPO& m, int i);
+    void env_left(Env& out, const Env& L, const Site& Abra, const Site& Aket, const MPO& m, int i,
+                  std::unique_ptr<EnvPlan>* plan = nullptr);
+    void env_right(Env& out, const Env& R, const Site& Abra, const Site& Aket, const MPO& m, int i,
+                   std::unique_ptr<EnvPlan>* plan = nullptr);
     void build_effop(EffOp& op, const Env& L, const Env& R, const TwoOp& O, const Two& ket,
                      const double* xket, const Two& bra, double* ybra);
-    void build_diag(const Env& L, const Env& R, const TwoOp& O, const Two& lay, double* d, double shift);
+    void build_diag(int i, const Env& L, const Env& R, const TwoOp& O, const Two& lay, double* d, double shift);
     void contract_sites(const Site& A, const Site& B, const Two& lay, double* out);
     double truncate(int i, bool forward, const Two& lay, const double* x, int M, Site& C);
     void next_guess(int i, bool forward, Site& C);

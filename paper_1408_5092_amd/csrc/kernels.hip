@@ -46,7 +46,7 @@ typedef double d4 __attribute__((ext_vector_type(4)));
 // k = lane/16 + 4 s), four k-steps of loads in flight per iteration, so a
 // group's terms run back to back without synchronisation.  Rows, columns
 // and k beyond the block are loaded as zeros.
-__global__ __launch_bounds__(256) void k_gemm_grouped(const GemmGroup* __restrict__ G, int ngroups,
+__global__ __launch_bounds__(256) void k_gemm_grouped(Bases bs, const GemmGroup* __restrict__ G, int ngroups,
                                                       const GemmTerm* __restrict__ T, int ntiles) {
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int tile = blockIdx.x * 4 + wave;
@@ -68,9 +68,11 @@ __global__ __launch_bounds__(256) void k_gemm_grouped(const GemmGroup* __restric
     for (int ti = 0; ti < g.nterms; ++ti) {
         const GemmTerm tm = T[g.term0 + ti];
         // element (row, kk) of op(A) at pa[kk * sa]; element (kk, col) of op(B) at pb[kk * sb]
-        const double* pa = tm.transA ? tm.A + ar : tm.A + (size_t)ar * tm.lda;
+        const double* A = bs.p[tm.sa] + tm.oa;
+        const double* B = bs.p[tm.sb] + tm.ob;
+        const double* pa = tm.transA ? A + ar : A + (size_t)ar * tm.lda;
         const size_t sa = tm.transA ? (size_t)tm.lda : 1;
-        const double* pb = tm.transB ? tm.B + (size_t)bc * tm.ldb : tm.B + bc;
+        const double* pb = tm.transB ? B + (size_t)bc * tm.ldb : B + bc;
         const size_t sb = tm.transB ? 1 : (size_t)tm.ldb;
         const double alpha = tm.alpha;
         const int k = tm.k;
@@ -98,41 +100,44 @@ __global__ __launch_bounds__(256) void k_gemm_grouped(const GemmGroup* __restric
     for (int e = 0; e < 4; ++e) {
         const int gi = row0 + lk + 4 * e, gj = col0 + li;
         if (gi < g.m && gj < g.n) {
-            double* c = g.C + (size_t)gi * g.ldc + gj;
+            double* c = bs.p[g.sc] + g.oc + (size_t)gi * g.ldc + gj;
             *c = g.accumulate ? *c + acc[e] : acc[e];
         }
     }
 }
 
 // ------------------------------------------------------------------- AXPY
-__global__ __launch_bounds__(256) void k_axpy_grouped(const AxpyGroup* __restrict__ G,
+__global__ __launch_bounds__(256) void k_axpy_grouped(Bases bs, const AxpyGroup* __restrict__ G,
                                                       const AxpyTerm* __restrict__ T) {
     const AxpyGroup g = G[blockIdx.x];
+    double* dst = bs.p[g.sd] + g.od;
     const int total = g.m * g.n;
     for (int e = threadIdx.x; e < total; e += blockDim.x) {
         const int i = e / g.n, j = e - i * g.n;
-        double s = g.accumulate ? g.dst[(size_t)i * g.ldd + j] : 0.0;
+        double s = g.accumulate ? dst[(size_t)i * g.ldd + j] : 0.0;
         for (int t = 0; t < g.nterms; ++t) {
             const AxpyTerm tm = T[g.term0 + t];
-            s += tm.alpha * (tm.trans ? tm.src[(size_t)j * tm.lds + i] : tm.src[(size_t)i * tm.lds + j]);
+            const double* src = bs.p[tm.ss] + tm.os;
+            s += tm.alpha * (tm.trans ? src[(size_t)j * tm.lds + i] : src[(size_t)i * tm.lds + j]);
         }
-        g.dst[(size_t)i * g.ldd + j] = s;
+        dst[(size_t)i * g.ldd + j] = s;
     }
 }
 
 // ------------------------------------------------------------------- DIAG
-__global__ __launch_bounds__(256) void k_diag_grouped(const DiagGroup* __restrict__ G,
+__global__ __launch_bounds__(256) void k_diag_grouped(Bases bs, const DiagGroup* __restrict__ G,
                                                       const DiagTerm* __restrict__ T) {
     const DiagGroup g = G[blockIdx.x];
+    double* dst = bs.p[g.sd] + g.od;
     const int total = g.m * g.n;
     for (int e = threadIdx.x; e < total; e += blockDim.x) {
         const int i = e / g.n, j = e - i * g.n;
         double s = g.shift;
         for (int t = 0; t < g.nterms; ++t) {
             const DiagTerm tm = T[g.term0 + t];
-            s += tm.c * tm.L[(size_t)i * tm.ls] * tm.R[(size_t)j * tm.rs];
+            s += tm.c * bs.p[tm.sl][tm.ol + (size_t)i * tm.ls] * bs.p[tm.sr][tm.orr + (size_t)j * tm.rs];
         }
-        g.dst[(size_t)i * g.ldd + j] = s;
+        dst[(size_t)i * g.ldd + j] = s;
     }
 }
 
@@ -826,23 +831,24 @@ KernelStats profile_stats(int kind) {
     return g_stats[kind];
 }
 
-void gemm_grouped(const GemmGroup* groups, int ngroups, const GemmTerm* terms, int ntiles, double flops,
-                  double bytes) {
+void gemm_grouped(const Bases& b, const GemmGroup* groups, int ngroups, const GemmTerm* terms, int ntiles,
+                  double flops, double bytes) {
     if (ntiles <= 0) return;
     Prof p(K_GEMM, flops, bytes);
-    hipLaunchKernelGGL(k_gemm_grouped, dim3((ntiles + 3) / 4), dim3(256), 0, g_stream, groups, ngroups, terms, ntiles);
+    hipLaunchKernelGGL(k_gemm_grouped, dim3((ntiles + 3) / 4), dim3(256), 0, g_stream, b, groups, ngroups, terms, ntiles);
     check(hipGetLastError(), "k_gemm_grouped");
 }
-void axpy_grouped(const AxpyGroup* groups, int ngroups, const AxpyTerm* terms, double flops, double bytes) {
+void axpy_grouped(const Bases& b, const AxpyGroup* groups, int ngroups, const AxpyTerm* terms, double flops,
+                  double bytes) {
     if (ngroups <= 0) return;
     Prof p(K_AXPY, flops, bytes);
-    hipLaunchKernelGGL(k_axpy_grouped, dim3(ngroups), dim3(256), 0, g_stream, groups, terms);
+    hipLaunchKernelGGL(k_axpy_grouped, dim3(ngroups), dim3(256), 0, g_stream, b, groups, terms);
     check(hipGetLastError(), "k_axpy_grouped");
 }
-void diag_grouped(const DiagGroup* groups, int ngroups, const DiagTerm* terms) {
+void diag_grouped(const Bases& b, const DiagGroup* groups, int ngroups, const DiagTerm* terms) {
     if (ngroups <= 0) return;
     Prof p(K_DIAG, 0, 0);
-    hipLaunchKernelGGL(k_diag_grouped, dim3(ngroups), dim3(256), 0, g_stream, groups, terms);
+    hipLaunchKernelGGL(k_diag_grouped, dim3(ngroups), dim3(256), 0, g_stream, b, groups, terms);
     check(hipGetLastError(), "k_diag_grouped");
 }
 void eig_reduce(const EigJob* jobs, int njobs, int nmax) {

@@ -42,7 +42,8 @@ class Result(C.Structure):
                 ("e2_sweep", C.c_double * 64), ("max_discarded", C.c_double),
                 ("cg_iters", C.c_int64), ("sigma_calls", C.c_int64),
                 ("sigma_flops", C.c_double), ("sigma_bytes", C.c_double),
-                ("t_total_s", C.c_double), ("flags", C.c_int32), ("t_phase", C.c_double * 6)]
+                ("t_total_s", C.c_double), ("flags", C.c_int32), ("t_phase", C.c_double * 6),
+                ("plan_builds", C.c_int64), ("plan_hits", C.c_int64)]
 
 
 _lib = None
