@@ -1514,6 +1514,7 @@ SweepResult Engine::sweep(const SweepParams& p) {
     trace_.clear();
     cg_tol2_ = p.cg_rel_tol * p.cg_rel_tol;
     cg_max_ = p.cg_max_iter;
+    clear_plans();  // plans are reused across the sweeps of one call only
     dev::sync();
     t0_ = dev::now();
     start(psi1_bonds_, psi1_guess_, p.M1);

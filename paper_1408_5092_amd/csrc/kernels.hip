@@ -111,16 +111,36 @@ __global__ __launch_bounds__(256) void k_axpy_grouped(Bases bs, const AxpyGroup*
                                                       const AxpyTerm* __restrict__ T) {
     const AxpyGroup g = G[blockIdx.x];
     double* dst = bs.p[g.sd] + g.od;
-    const int total = g.m * g.n;
+    // element e = i n + j, advanced by the block size without dividing
+    const int total = g.m * g.n, di = blockDim.x / g.n, dj = blockDim.x - di * g.n;
+    int i = threadIdx.x / g.n, j = threadIdx.x - i * g.n;
     for (int e = threadIdx.x; e < total; e += blockDim.x) {
-        const int i = e / g.n, j = e - i * g.n;
         double s = g.accumulate ? dst[(size_t)i * g.ldd + j] : 0.0;
-        for (int t = 0; t < g.nterms; ++t) {
+        // eight terms' loads in flight, added in term order
+        int t = 0;
+        for (; t + 8 <= g.nterms; t += 8) {
+            double v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const AxpyTerm tm = T[g.term0 + t + u];
+                const double* src = bs.p[tm.ss] + tm.os;
+                v[u] = tm.alpha * (tm.trans ? src[(size_t)j * tm.lds + i] : src[(size_t)i * tm.lds + j]);
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) s += v[u];
+        }
+        for (; t < g.nterms; ++t) {
             const AxpyTerm tm = T[g.term0 + t];
             const double* src = bs.p[tm.ss] + tm.os;
             s += tm.alpha * (tm.trans ? src[(size_t)j * tm.lds + i] : src[(size_t)i * tm.lds + j]);
         }
         dst[(size_t)i * g.ldd + j] = s;
+        i += di;
+        j += dj;
+        if (j >= g.n) {
+            j -= g.n;
+            ++i;
+        }
     }
 }
 
@@ -129,15 +149,21 @@ __global__ __launch_bounds__(256) void k_diag_grouped(Bases bs, const DiagGroup*
                                                       const DiagTerm* __restrict__ T) {
     const DiagGroup g = G[blockIdx.x];
     double* dst = bs.p[g.sd] + g.od;
-    const int total = g.m * g.n;
+    const int total = g.m * g.n, di = blockDim.x / g.n, dj = blockDim.x - di * g.n;
+    int i = threadIdx.x / g.n, j = threadIdx.x - i * g.n;
     for (int e = threadIdx.x; e < total; e += blockDim.x) {
-        const int i = e / g.n, j = e - i * g.n;
         double s = g.shift;
         for (int t = 0; t < g.nterms; ++t) {
             const DiagTerm tm = T[g.term0 + t];
             s += tm.c * bs.p[tm.sl][tm.ol + (size_t)i * tm.ls] * bs.p[tm.sr][tm.orr + (size_t)j * tm.rs];
         }
         dst[(size_t)i * g.ldd + j] = s;
+        i += di;
+        j += dj;
+        if (j >= g.n) {
+            j -= g.n;
+            ++i;
+        }
     }
 }
 
@@ -238,10 +264,12 @@ __global__ __launch_bounds__(1024) void k_eig_reduce(const EigJob* __restrict__ 
         double part = 0.0;
         for (int i = k + 1 + lane; i < n; i += 64) part += sp[i] * sv[i];
         const double K = 0.5 * tau * wave_sum(part);
-        for (int e = tid; e < m * m; e += 1024) {
-            const int i = k + 1 + e / m, j = k + 1 + e % m;
-            const double vi = sv[i], vj = sv[j];
-            M[i * ld + j] -= vi * (sp[j] - K * vj) + (sp[i] - K * vi) * vj;
+        for (int i = k + 1 + (tid >> 6); i < n; i += 16) {
+            const double vi = sv[i], wi = sp[i] - K * vi;
+            for (int j = k + 1 + lane; j < n; j += 64) {
+                const double vj = sv[j];
+                M[i * ld + j] -= vi * (sp[j] - K * vj) + wi * vj;
+            }
         }
         __syncthreads();
     }
@@ -302,7 +330,11 @@ __global__ __launch_bounds__(1024) void k_eig_reduce(const EigJob* __restrict__ 
             if (fabs(q) <= piv) q = -piv;
             cnt = q < 0.0;
             for (int i = 1; i < n; ++i) {
-                q = sd[i] - x - sp[i - 1] / q;
+                // hardware reciprocal refined by one Newton step: each count
+                // stays the exact count of a matrix within a few ulps of T
+                double r = __builtin_amdgcn_rcp(q);
+                r = fma(r, fma(-q, r, 1.0), r);
+                q = sd[i] - x - sp[i - 1] * r;
                 if (fabs(q) <= piv) q = -piv;
                 cnt += q < 0.0;
             }
@@ -364,7 +396,27 @@ __device__ void tri_solve(const double* sd, const double* se, int n, double sigm
     if (fabs(bi) < guard) bi = bi < 0.0 ? -guard : guard;
     double y2 = 0.0, y1 = yi / bi;
     Y(n - 1) = y1;
-    for (int i = n - 2; i >= 0; --i) {
+    // back substitution, the rows of U and y for four steps loaded up front
+    int i = n - 2;
+    for (; i >= 3; i -= 4) {
+        double u0[4], u1[4], u2[4], yv[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const double* Ui = U + (size_t)3 * (i - q) * ustride;
+            u0[q] = Ui[0];
+            u1[q] = Ui[ustride];
+            u2[q] = Ui[2 * ustride];
+            yv[q] = Y(i - q);
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const double y0 = (yv[q] - u1[q] * y1 - u2[q] * y2) / u0[q];
+            Y(i - q) = y0;
+            y2 = y1;
+            y1 = y0;
+        }
+    }
+    for (; i >= 0; --i) {
         const double* Ui = U + (size_t)3 * i * ustride;
         const double y0 = (Y(i) - Ui[ustride] * y1 - Ui[2 * ustride] * y2) / Ui[0];
         Y(i) = y0;
@@ -373,21 +425,41 @@ __device__ void tri_solve(const double* sd, const double* se, int n, double sigm
     }
 }
 
+// LDS use of k_eig_vectors (doubles): the basis Y (n x (k+1)) and Gram matrix
+// G (k x (k+1)) when LDS-resident, then per block of rb reflectors: the
+// vectors (rb x n), V^T Y and T V^T Y (rb x (k+1) each), T and V^T V
+// (rb x rb each) and the block's tau.
+__host__ __device__ inline size_t eigv_lds_words(int n, int k, int rb, bool resident) {
+    size_t w = (size_t)rb * n + 2 * (size_t)rb * (k + 1) + 2 * (size_t)rb * rb + rb;
+    if (resident) w += (size_t)n * (k + 1) + (size_t)k * (k + 1);
+    return w;
+}
+
 template <bool LDSRES>
-__global__ __launch_bounds__(1024) void k_eig_vectors(const EigJob* __restrict__ jobs, int* __restrict__ status) {
+__global__ __launch_bounds__(1024) void k_eig_vectors(const EigJob* __restrict__ jobs, int* __restrict__ status,
+                                                      int rb, int u_lds) {
     extern __shared__ __align__(16) double dyn[];
-    __shared__ double sd[EIG_MAXN], se[EIG_MAXN], sw[EIG_MAXN], sv[EIG_MAXN], sv2[EIG_MAXN], sp[EIG_MAXN];
+    __shared__ double sd[EIG_MAXN], se[EIG_MAXN], sw[EIG_MAXN];
     __shared__ int s_fail;
     const EigJob J = jobs[blockIdx.x];
     const int n = J.n, k = J.k;
     if (k <= 0) return;
     const int tid = threadIdx.x, lane = tid & 63;
-    // Y (n x k): LDS row major with rows padded to k + 1, or the first k
-    // columns of A
-    const int ldy = LDSRES ? k + 1 : n;
+    // Y (n x k) row major: in LDS with rows padded to k + 1, or the first k
+    // columns of A; G (k x k, upper triangle used) in LDS or in t
+    const int ldy = LDSRES ? k + 1 : n, ldg = LDSRES ? k + 1 : k;
+    // 3 n k: rows of U of the inverse-iteration solves, in the LDS the later
+    // phases use (after Y) when it fits
+    double* U = u_lds ? dyn + (LDSRES ? (size_t)n * (k + 1) : 0) : J.t + 2 * n;
     double* Yb = LDSRES ? dyn : J.A;
-    double* U = J.t + 2 * n;              // 3 n k
-    double* G = U + (size_t)3 * n * k;   // k x k
+    double* G = LDSRES ? dyn + (size_t)n * (k + 1) : J.t + 2 * n + (size_t)3 * n * k;
+    double* blk = LDSRES ? G + (size_t)k * (k + 1) : dyn;
+    double* Vb = blk;                        // rb x n
+    double* Zb = Vb + (size_t)rb * n;        // rb x (k + 1)
+    double* Wb = Zb + (size_t)rb * (k + 1);  // rb x (k + 1)
+    double* Tb = Wb + (size_t)rb * (k + 1);  // rb x rb
+    double* Cb = Tb + (size_t)rb * rb;       // rb x rb
+    double* tb = Cb + (size_t)rb * rb;       // rb
     for (int i = tid; i < n; i += 1024) {
         sd[i] = J.t[i];
         se[i] = J.t[n + i];
@@ -421,20 +493,24 @@ __global__ __launch_bounds__(1024) void k_eig_vectors(const EigJob* __restrict__
                     if (pass < 3) tri_solve(sd, se, n, sw[c], guard, Yc, U + c, k);
                     double nrm = 0.0;
                     for (int i = 0; i < n; ++i) nrm += Yc(i) * Yc(i);
-                    const double s = nrm > 0.0 ? 1.0 / sqrt(nrm) : 0.0;
-                    for (int i = 0; i < n; ++i) Yc(i) *= s;
+                    const double sc = nrm > 0.0 ? 1.0 / sqrt(nrm) : 0.0;
+                    for (int i = 0; i < n; ++i) Yc(i) *= sc;
                 }
             }
         }
     }
     __syncthreads();
-    // ---- two passes of Cholesky QR: G = Y^T Y = R^T R, Y <- Y R^-1
+    // ---- Cholesky QR: G = Y^T Y = R^T R, Y <- Y R^-1; a second pass when
+    // the first Gram matrix was off the identity by more than 1e-6
     const int T4 = (k + 3) / 4, ntile = T4 * (T4 + 1) / 2;
+    __shared__ int s_again;
+    if (tid == 0) s_again = 0;
     for (int pass = 0; pass < 2; ++pass) {
+        if (pass == 1 && !s_again) break;
         for (int t = tid; t < ntile; t += 1024) {
             int ta = 0, rem = t;
             while (rem >= T4 - ta) { rem -= T4 - ta; ++ta; }
-            const int tb = ta + rem, a0 = ta * 4, b0 = tb * 4;
+            const int tbi = ta + rem, a0 = ta * 4, b0 = tbi * 4;
             double acc[4][4] = {};
             for (int i = 0; i < n; ++i) {
                 double ya[4], yb[4];
@@ -448,33 +524,51 @@ __global__ __launch_bounds__(1024) void k_eig_vectors(const EigJob* __restrict__
 #pragma unroll
                     for (int q = 0; q < 4; ++q) acc[p][q] += ya[p] * yb[q];
             }
+            bool off = false;
 #pragma unroll
             for (int p = 0; p < 4; ++p)
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
                     const int a = a0 + p, b = b0 + q;
-                    if (a < k && b < k && a <= b) G[(size_t)a * k + b] = acc[p][q];
+                    if (a < k && b < k && a <= b) {
+                        G[(size_t)a * ldg + b] = acc[p][q];
+                        off |= fabs(acc[p][q] - (a == b ? 1.0 : 0.0)) > 1e-6;
+                    }
                 }
+            if (off) s_again = 1;
         }
         __syncthreads();
-        // upper Cholesky factor in place, wave 0
+        // upper Cholesky factor in place by wave 0 (the diagonal keeps 1 / R_cc)
         if (tid < 64) {
             for (int c = 0; c < k; ++c) {
-                const double pv = G[(size_t)c * k + c];
+                const double pv = G[(size_t)c * ldg + c];
                 if (!(pv > 1e-24)) {
                     if (lane == 0) s_fail = 1;
                     break;
                 }
-                const double r = sqrt(pv), ri = 1.0 / r;
-                for (int l = c + 1 + lane; l < k; l += 64) G[(size_t)c * k + l] *= ri;
-                __threadfence_block();
-                if (lane == 0) G[(size_t)c * k + c] = r;
+                const double ri = 1.0 / sqrt(pv);
+                for (int l = c + 1 + lane; l < k; l += 64) G[(size_t)c * ldg + l] *= ri;
+                if (!LDSRES) __threadfence_block();
+                // trailing update over the (m x m) square, upper part; the pair
+                // index advances by 64 without dividing
                 const int m = k - c - 1;
-                for (int e = lane; e < m * m; e += 64) {
-                    const int i = c + 1 + e / m, l = c + 1 + e % m;
-                    if (l >= i) G[(size_t)i * k + l] -= G[(size_t)c * k + i] * G[(size_t)c * k + l];
+                if (m > 0) {
+                    const int di = 64 / m, dj = 64 - di * m;
+                    int i = lane / m, l = lane - i * m;
+                    for (int e = lane; e < m * m; e += 64) {
+                        if (l >= i)
+                            G[(size_t)(c + 1 + i) * ldg + c + 1 + l] -=
+                                G[(size_t)c * ldg + c + 1 + i] * G[(size_t)c * ldg + c + 1 + l];
+                        i += di;
+                        l += dj;
+                        if (l >= m) {
+                            l -= m;
+                            ++i;
+                        }
+                    }
                 }
-                __threadfence_block();
+                if (lane == 0) G[(size_t)c * ldg + c] = ri;
+                if (!LDSRES) __threadfence_block();
             }
         }
         __syncthreads();
@@ -483,9 +577,9 @@ __global__ __launch_bounds__(1024) void k_eig_vectors(const EigJob* __restrict__
         for (int i = tid; i < n; i += 1024) {
             double* yr = Yb + (size_t)i * ldy;
             for (int l = 0; l < k; ++l) {
-                double s = yr[l];
-                for (int m2 = 0; m2 < l; ++m2) s -= yr[m2] * G[(size_t)m2 * k + l];
-                yr[l] = s / G[(size_t)l * k + l];
+                double sacc = yr[l];
+                for (int m2 = 0; m2 < l; ++m2) sacc -= yr[m2] * G[(size_t)m2 * ldg + l];
+                yr[l] = sacc * G[(size_t)l * ldg + l];
             }
         }
         __syncthreads();
@@ -494,38 +588,61 @@ __global__ __launch_bounds__(1024) void k_eig_vectors(const EigJob* __restrict__
         if (tid == 0) atomicAdd(status, 1);
         return;
     }
-    // ---- back-transform: Y <- H_0 H_1 ... H_{n-3} Y, the next reflector
-    // staged while the current one is applied
+    // ---- back-transform Y <- H_0 H_1 ... H_{n-3} Y by blocks of rb reflectors,
+    // last block first: H_lo ... H_hi = I - V T V^T (compact WY form)
     const double* V = J.V;
-    auto stage = [&](int r, double* dst) {
-        for (int i = r + 1 + tid; i < n; i += 1024) dst[i] = (i == r + 1) ? 1.0 : V[(size_t)r * n + i];
-    };
-    if (n >= 3) stage(n - 3, sv);
-    __syncthreads();
-    double* vcur = sv;
-    double* vnext = sv2;
-    for (int r = n - 3; r >= 0; --r) {
-        const double tau = V[(size_t)r * n + r];
-        const int m = n - r - 1;
-        if (tau != 0.0) {
-            for (int e = tid; e < k * 8; e += 1024) {
-                const int l = e >> 3, g = e & 7;
-                double s = 0.0;
-                for (int i = r + 1 + g; i < n; i += 8) s += vcur[i] * Yb[(size_t)i * ldy + l];
-                s = group8_sum(s);
-                if (g == 0) sp[l] = tau * s;
-            }
-            __syncthreads();
-            for (int e = tid; e < m * k; e += 1024) {
-                const int i = r + 1 + e / k, l = e % k;
-                Yb[(size_t)i * ldy + l] -= vcur[i] * sp[l];
+    for (int hi = n - 3; hi >= 0; hi -= rb) {
+        const int lo = max(0, hi - rb + 1), nb = hi - lo + 1;
+        for (int e = tid; e < nb * n; e += 1024) {
+            const int j = e / n, i = e - j * n, r = lo + j;
+            Vb[e] = i <= r ? 0.0 : (i == r + 1 ? 1.0 : V[(size_t)r * n + i]);
+        }
+        for (int j = tid; j < nb; j += 1024) tb[j] = V[(size_t)(lo + j) * n + lo + j];
+        __syncthreads();
+        for (int e = tid; e < nb * nb; e += 1024) {  // C = V^T V (strict upper part)
+            const int a = e / nb, b = e - a * nb;
+            if (a < b) {
+                double sacc = 0.0;
+                for (int i = lo + b + 1; i < n; ++i) sacc += Vb[(size_t)a * n + i] * Vb[(size_t)b * n + i];
+                Cb[e] = sacc;
             }
         }
-        if (r > 0) stage(r - 1, vnext);
+        for (int e = tid; e < nb * k * 4; e += 1024) {  // Z = V^T Y, four threads per entry
+            const int q = e & 3, jl = e >> 2, j = jl / k, l = jl - j * k;
+            double sacc = 0.0;
+            for (int i = lo + j + 1 + q; i < n; i += 4) sacc += Vb[(size_t)j * n + i] * Yb[(size_t)i * ldy + l];
+            sacc += __shfl_xor(sacc, 1, 4);
+            sacc += __shfl_xor(sacc, 2, 4);
+            if (q == 0) Zb[(size_t)j * (k + 1) + l] = sacc;
+        }
         __syncthreads();
-        double* t = vcur;
-        vcur = vnext;
-        vnext = t;
+        if (tid < 64) {  // T, one column at a time; lane a owns row a
+            for (int j = 0; j < nb; ++j) {
+                if (lane < j) {
+                    double sacc = 0.0;
+                    for (int b = lane; b < j; ++b) sacc += Tb[lane * rb + b] * Cb[b * nb + j];
+                    Tb[lane * rb + j] = -tb[j] * sacc;
+                }
+                if (lane == j) Tb[j * rb + j] = tb[j];
+            }
+        }
+        __syncthreads();
+        for (int e = tid; e < nb * k; e += 1024) {  // W = T Z
+            const int a = e / k, l = e - a * k;
+            double sacc = 0.0;
+            for (int b = a; b < nb; ++b) sacc += Tb[a * rb + b] * Zb[(size_t)b * (k + 1) + l];
+            Wb[(size_t)a * (k + 1) + l] = sacc;
+        }
+        __syncthreads();
+        for (int i = lo + 1 + (tid >> 6); i < n; i += 16) {  // Y -= V W, rows by wave
+            const int jmax = min(nb, i - lo);
+            for (int l = lane; l < k; l += 64) {
+                double sacc = 0.0;
+                for (int j = 0; j < jmax; ++j) sacc += Vb[(size_t)j * n + i] * Wb[(size_t)j * (k + 1) + l];
+                Yb[(size_t)i * ldy + l] -= sacc;
+            }
+        }
+        __syncthreads();
     }
     if (LDSRES) {
         for (int e = tid; e < n * k; e += 1024) {
@@ -671,15 +788,16 @@ void set_device(int device, void* stream) {
     if (std::string(prop.gcnArchName).rfind("gfx950", 0) != 0)
         throw Error{MPSPT_E_NODEV, std::string("device is ") + prop.gcnArchName + ", the library is built for gfx950"};
     g_stream = static_cast<hipStream_t>(stream);
-    // dynamic LDS left for the eigensolver's matrix (or basis) next to its
-    // ~25 KB of static shared memory
+    // dynamic LDS left for the eigensolver next to at most ~25 KB of static
+    // shared memory
     int lds = 0;
     check(hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, device), "hipDeviceGetAttribute");
     const long budget = ((long)lds - 6 * EIG_MAXN * 8 - 1024) / 16 * 16;
     if (budget < 4096) throw Error{MPSPT_E_NODEV, "not enough LDS for the eigensolver"};
     g_lds_budget = (size_t)budget;
     const void* ks[] = {reinterpret_cast<const void*>(&k_eig_reduce<true>),
-                        reinterpret_cast<const void*>(&k_eig_vectors<true>)};
+                        reinterpret_cast<const void*>(&k_eig_vectors<true>),
+                        reinterpret_cast<const void*>(&k_eig_vectors<false>)};
     for (const void* f : ks)
         check(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)budget), "hipFuncSetAttribute");
 }
@@ -867,16 +985,26 @@ void eig_vectors(const EigJob* jobs, int njobs, int nmax, int kmax, int* status)
     if (njobs <= 0) return;
     if (nmax > EIG_MAXN || kmax > nmax) throw Error{MPSPT_E_ARG, "eigensolver limited to k <= n <= 512"};
     Prof p(K_EIGV, 0, 0);
+    const size_t words = g_lds_budget / sizeof(double);
+    const size_t uw = (size_t)3 * nmax * kmax;  // solve rows, aliasing the later phases' LDS
     if (eig_vectors_class(nmax, kmax) == 0) {
-        const size_t shm = (size_t)nmax * (kmax + 1) * sizeof(double);
-        hipLaunchKernelGGL(k_eig_vectors<true>, dim3(njobs), dim3(1024), shm, g_stream, jobs, status);
+        const size_t base = (size_t)nmax * (kmax + 1);
+        const size_t need = eigv_lds_words(nmax, kmax, 16, true);
+        const int u_lds = base + uw <= words ? 1 : 0;
+        const size_t shm = std::max(need, u_lds ? base + uw : 0) * sizeof(double);
+        hipLaunchKernelGGL(k_eig_vectors<true>, dim3(njobs), dim3(1024), shm, g_stream, jobs, status, 16, u_lds);
     } else {
-        hipLaunchKernelGGL(k_eig_vectors<false>, dim3(njobs), dim3(1024), 0, g_stream, jobs, status);
+        int rb = 16;
+        while (rb > 1 && eigv_lds_words(nmax, kmax, rb, false) > words) --rb;
+        const size_t need = eigv_lds_words(nmax, kmax, rb, false);
+        const int u_lds = uw <= words ? 1 : 0;
+        const size_t shm = std::max(need, u_lds ? uw : 0) * sizeof(double);
+        hipLaunchKernelGGL(k_eig_vectors<false>, dim3(njobs), dim3(1024), shm, g_stream, jobs, status, rb, u_lds);
     }
     check(hipGetLastError(), "k_eig_vectors");
 }
 int eig_reduce_class(int n) { return (size_t)n * (n + 1) * sizeof(double) <= g_lds_budget ? 0 : 1; }
-int eig_vectors_class(int n, int k) { return (size_t)n * (k + 1) * sizeof(double) <= g_lds_budget ? 0 : 1; }
+int eig_vectors_class(int n, int k) { return eigv_lds_words(n, k, 16, true) * sizeof(double) <= g_lds_budget ? 0 : 1; }
 size_t eig_work(int n) { return 2 * (size_t)n + 4 * (size_t)n * n; }
 
 void dot(const double* a, const double* b, size_t n, double* scal, int slot, double* partials) {
