@@ -83,6 +83,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--copy-calibration", type=int, default=0,
+                    help="bytes of one plain device-to-device copy issued before the timed region, to scale "
+                         "hardware traffic counters (0: none)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU layout of the "
@@ -107,6 +110,13 @@ def main():
     torch.cuda.synchronize()
     t_setup = time.perf_counter() - t_setup
     print(f"[bench] setup {t_setup:.2f}s (DMRG Psi0 E={e_gs:.10f})", file=sys.stderr, flush=True)
+
+    if args.copy_calibration > 0:
+        src = torch.empty(args.copy_calibration // 8, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     # converged reference of the same decomposition and bond dimension (untimed)
     ref = ctx.sweep(M1, n_sweeps=0, max_sweeps=12, e_tol=1e-10, compute_e3=False)

@@ -159,7 +159,9 @@ mpspt_status mpspt_get_site(mpspt_ctx *ctx, int32_t which, int32_t site, size_t 
                             int32_t *dims);
 
 /* Host-only validation hook: contract one of the library's MPOs
- * (which = 0: H0, 1: the part of V acting on Psi0, 2: V) to a dense
+ * (which = 0: H0, 1: the part of V acting on Psi0, 2: V, 3: the part of V
+ * that keeps the number of virtual electrons within one of itself, used for
+ * E3 = <Psi1|V|Psi1>) to a dense
  * 4^n x 4^n matrix, n = k_a + k_v <= 6, site 0 most significant.
  * eri as in mpspt_load_integrals_eri.  Needs no device. */
 mpspt_status mpspt_mpo_dense(int32_t k_a, int32_t k_v, const double *h, const double *eri,

@@ -298,8 +298,11 @@ mpspt_status mpspt_mpo_dims(int32_t k_a, int32_t k_v, const double* h, const dou
         const size_t k = k_a + k_v;
         check_finite(eri, k * k * k * k, "eri");
         check_finite(eps_virt, k_v, "eps_virt");
-        if (which < 0 || which > 2) throw argerr("which must be 0, 1 or 2");
-        mpspt::OpKind kind = which == 0 ? mpspt::OpKind::H0 : which == 1 ? mpspt::OpKind::VPsi0 : mpspt::OpKind::VFull;
+        if (which < 0 || which > 3) throw argerr("which must be 0, 1, 2 or 3");
+        mpspt::OpKind kind = which == 0   ? mpspt::OpKind::H0
+                             : which == 1 ? mpspt::OpKind::VPsi0
+                             : which == 2 ? mpspt::OpKind::VFull
+                                          : mpspt::OpKind::VPsi1;
         mpspt::MPO m = mpspt::build_mpo(kind, k_a, k_v, std::vector<double>(h, h + k * k),
                                         std::vector<double>(eri, eri + k * k * k * k),
                                         std::vector<double>(eps_virt, eps_virt + k_v));
@@ -316,11 +319,14 @@ mpspt_status mpspt_mpo_dense(int32_t k_a, int32_t k_v, const double* h, const do
         const size_t k = n;
         check_finite(eri, k * k * k * k, "eri");
         check_finite(eps_virt, k_v, "eps_virt");
-        if (which < 0 || which > 2) throw argerr("which must be 0, 1 or 2");
+        if (which < 0 || which > 3) throw argerr("which must be 0, 1, 2 or 3");
         size_t dim = 1;
         for (int i = 0; i < n; ++i) dim *= 4;
         if (!out || cap < dim * dim) throw argerr("output buffer too small");
-        mpspt::OpKind kind = which == 0 ? mpspt::OpKind::H0 : which == 1 ? mpspt::OpKind::VPsi0 : mpspt::OpKind::VFull;
+        mpspt::OpKind kind = which == 0   ? mpspt::OpKind::H0
+                             : which == 1 ? mpspt::OpKind::VPsi0
+                             : which == 2 ? mpspt::OpKind::VFull
+                                          : mpspt::OpKind::VPsi1;
         mpspt::MPO m = mpspt::build_mpo(kind, k_a, k_v, std::vector<double>(h, h + k * k),
                                         std::vector<double>(eri, eri + k * k * k * k),
                                         std::vector<double>(eps_virt, eps_virt + k_v));

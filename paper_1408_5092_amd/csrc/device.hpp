@@ -99,6 +99,15 @@ void d2h(void* dst, const void* src, size_t bytes);  // synchronous
 void d2d(void* dst, const void* src, size_t bytes);
 void zero(void* p, size_t bytes);
 void sync();
+// Ordered device-to-host copy into pinned host memory that does not wait;
+// event_record/event_wait mark and await its completion.
+void* host_alloc(size_t bytes);  // pinned
+void host_free(void* p);
+void d2h_async(void* dst, const void* src, size_t bytes);
+void* event_create();
+void event_destroy(void* e);
+void event_record(void* e);
+void event_wait(void* e);
 double now();  // host seconds
 
 // flops / bytes: algorithmic work of the launch, used only by the profiler
@@ -127,7 +136,9 @@ int eig_vectors_class(int n, int k);
 size_t eig_work(int n);
 
 // Vector kernels over length-n double vectors.  `scal` is a small device
-// array of scalars (layout in kernels.hip); all reductions are fixed-order.
+// array of scalars; `partials` is the reduction workspace of kPartialsWords
+// doubles whose last words (a counter) must be zero before first use and are
+// left zero by every call.  All reductions are fixed-order, one launch each.
 enum Scalar { S_PQ = 0, S_RZ0 = 1, S_RZ1 = 2, S_RR = 3, S_BB = 4, S_DOT = 5, S_N = 8 };
 void dot(const double* a, const double* b, size_t n, double* scal, int slot, double* partials);
 // r = -b - q ; z = r / d ; p = z ; scal[RZ0] = r.z ; scal[RR] = r.r ; scal[BB] = b.b
@@ -135,17 +146,19 @@ void cg_init(double* r, double* z, double* p, const double* b, const double* q, 
              size_t n, double* scal, double* partials);
 // q -= shift * p ; scal[PQ] = p.q
 void cg_shift_dot(double* q, const double* p, double shift, size_t n, double* scal, double* partials);
-// alpha = rz_cur / pq ; x += alpha p ; r -= alpha q ; z = r / d ; scal[rz_new] = r.z ; scal[RR] = r.r
+// alpha = rz_cur / pq (0 if pq = 0) ; x += alpha p ; r -= alpha q ; z = r / d ;
+// scal[rz_new] = r.z ; scal[RR] = r.r
 void cg_update(double* x, double* r, double* z, const double* p, const double* q, const double* d,
                size_t n, double* scal, int rz_cur, int rz_new, double* partials);
-// p = z + (rz_new / rz_cur) p
+// p = z + (rz_new / rz_cur) p (beta = 0 if rz_cur = 0)
 void cg_direction(double* p, const double* z, size_t n, const double* scal, int rz_cur, int rz_new);
 // y = a x + b y
 void axpby(double* y, const double* x, double a, double b, size_t n);
 // t = r / (theta - d), with |theta - d| floored at 1e-8 (Davidson correction)
 void davidson_precond(double* t, const double* r, const double* d, double theta, size_t n);
 
-constexpr int kPartials = 512;  // size of the partials workspace (doubles)
+constexpr int kPartials = 512;        // block sums: four rows of kPartials / 4
+constexpr int kPartialsWords = 520;   // with the arrival counter after them
 
 }  // namespace dev
 }  // namespace mpspt

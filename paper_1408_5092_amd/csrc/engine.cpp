@@ -486,6 +486,17 @@ void Engine::set_partition(std::vector<double> eps) {
     have_psi0 = have_psi1 = false;
 }
 
+void Engine::ensure_partials() {
+    if (partials_.n >= (size_t)dev::kPartialsWords) return;
+    partials_.ensure(dev::kPartialsWords);
+    dev::zero(partials_.p, dev::kPartialsWords * sizeof(double));
+}
+
+Engine::~Engine() {
+    dev::host_free(hsc_);
+    for (void* e : ev_) dev::event_destroy(e);
+}
+
 void Engine::clear_plans() {
     for (auto& v : eff_plans_) v.clear();
     for (auto& v : env_plans_) v.clear();
@@ -496,6 +507,7 @@ void Engine::build_mpos() {
     clear_plans();
     mpo_h0_ = build_mpo(OpKind::H0, k_a_, k_v_, h_, eri_, eps_);
     mpo_v_ = build_mpo(OpKind::VPsi0, k_a_, k_v_, h_, eri_, eps_);
+    mpo_e3_ = build_mpo(OpKind::VPsi1, k_a_, k_v_, h_, eri_, eps_);
     twoop_cache_[0].clear();
     clear_plans();
     twoop_cache_[1].clear();
@@ -1306,7 +1318,7 @@ int Engine::solve(int i, double& e2) {
     const Two& lay = xlay_;
     const size_t n = lay.size;
     for (DevBuf* b : {&x_, &b_, &d_, &r_, &z_, &p_, &q_}) b->ensure(std::max<size_t>(n, 1));
-    partials_.ensure(dev::kPartials);
+    ensure_partials();
     scal_.ensure(dev::S_N);
     double t = dev::now();
     const TwoOp& O = twoop(0, i);
@@ -1360,18 +1372,42 @@ int Engine::solve(int i, double& e2) {
             res_.flags |= 1;
             break;
         }
+        // Iteration k's scalars go to pinned slot k % 2; the host examines
+        // iteration k - 1 while iteration k runs, so the device never waits
+        // for the host.  When k - 1 has converged, x carries the one extra
+        // iteration k.
+        if (!hsc_) {
+            hsc_ = static_cast<double*>(dev::host_alloc(2 * dev::S_N * sizeof(double)));
+            for (void*& e : ev_) e = dev::event_create();
+        }
         int cur = dev::S_RZ0, nxt = dev::S_RZ1;
-        while (it < cg_max_) {
-            apply();
-            dev::cg_update(x_.p, r_.p, z_.p, p_.p, q_.p, d_.p, n, scal_.p, cur, nxt, partials_.p);
-            dev::d2h(sc, scal_.p, sizeof(sc));
-            ++it;
-            if (!(sc[dev::S_PQ] > 0.0))
-                throw err(MPSPT_E_INDEFINITE, "CG met p.Ap <= 0: H0 - E0 is not positive definite on the local space");
-            rr = sc[dev::S_RR];
-            if (rr <= cg_tol2_ * bb) break;
-            dev::cg_direction(p_.p, z_.p, n, scal_.p, cur, nxt);
-            std::swap(cur, nxt);
+        int seen = it;  // iterations before `seen` have been examined
+        bool conv = false;
+        while (!conv) {
+            if (it < cg_max_) {
+                apply();
+                dev::cg_update(x_.p, r_.p, z_.p, p_.p, q_.p, d_.p, n, scal_.p, cur, nxt, partials_.p);
+                dev::d2h_async(hsc_ + (it & 1) * dev::S_N, scal_.p, dev::S_N * sizeof(double));
+                dev::event_record(ev_[it & 1]);
+                dev::cg_direction(p_.p, z_.p, n, scal_.p, cur, nxt);
+                std::swap(cur, nxt);
+                ++it;
+            } else if (seen == it) {
+                break;  // iteration cap
+            }
+            // examine the oldest unexamined iteration, unless it is the one just issued
+            while (seen < it && (seen < it - 1 || it >= cg_max_)) {
+                dev::event_wait(ev_[seen & 1]);
+                const double* h = hsc_ + (seen & 1) * dev::S_N;
+                ++seen;
+                if (!(h[dev::S_PQ] > 0.0))
+                    throw err(MPSPT_E_INDEFINITE, "CG met p.Ap <= 0: H0 - E0 is not positive definite on the local space");
+                rr = h[dev::S_RR];
+                if (rr <= cg_tol2_ * bb) {
+                    conv = true;
+                    break;
+                }
+            }
         }
         dev::d2d(p_.p, x_.p, n * sizeof(double));
         apply();  // q = A x, scal[PQ] = x.A x
@@ -1414,7 +1450,7 @@ void Engine::next_guess(int i, bool forward, Site& C) {
 }
 
 double Engine::e3_final(int window) {
-    MPO mf = build_mpo(OpKind::VFull, k_a_, k_v_, h_, eri_, eps_);
+    const MPO& mf = mpo_e3_;
     Env R = trivial_env(A_[n_ - 1].R, A_[n_ - 1].R);
     for (int j = n_ - 1; j >= window + 2; --j) {
         Env R2;
@@ -1608,7 +1644,7 @@ int Engine::davidson(int i, double& e) {
     for (DevBuf* b : {&x_, &d_, &r_, &z_, &p_, &q_}) b->ensure(std::max<size_t>(n, 1));
     dav_V_.ensure(std::max<size_t>(n, 1) * kMax);
     dav_AV_.ensure(std::max<size_t>(n, 1) * kMax);
-    partials_.ensure(dev::kPartials);
+    ensure_partials();
     scal_.ensure(dev::S_N);
     const TwoOp& O = twoop(0, i);
     build_diag(i, LH_[i], RH_[i + 2], O, lay, d_.p, 0.0);

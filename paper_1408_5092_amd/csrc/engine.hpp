@@ -240,6 +240,10 @@ struct SweepResult {
 
 class Engine {
   public:
+    Engine() = default;
+    Engine(const Engine&) = delete;
+    Engine& operator=(const Engine&) = delete;
+    ~Engine();
     // inputs
     void set_integrals(int k_a, int k_v, std::vector<double> h, std::vector<double> eri);
     void set_partition(std::vector<double> eps);
@@ -264,7 +268,7 @@ class Engine {
     // problem
     int k_a_ = 0, k_v_ = 0, n_ = 0, N_ = 0, tsz_ = 0;
     std::vector<double> h_, eri_, eps_;
-    MPO mpo_h0_, mpo_v_;
+    MPO mpo_h0_, mpo_v_, mpo_e3_;  // H0, V on Psi0, V within the Psi1 space (E3)
     double E0_ = 0;
     // states
     std::vector<Site> P0_;      // extended Psi0
@@ -312,6 +316,9 @@ class Engine {
     std::vector<std::unique_ptr<EnvPlan>> env_plans_[4];  // LH, LV, RH, RV updates
     std::vector<std::unique_ptr<DiagPlan>> diag_plans_;
     void clear_plans();
+    void ensure_partials();
+    double* hsc_ = nullptr;  // pinned host copies of the CG scalars, two slots
+    void* ev_[2] = {nullptr, nullptr};
     EffOp& effop(int r, int i, const Env& L, const Env& R, const TwoOp& O, const Two& ket, const double* xket,
                  const Two& bra, double* ybra);
     void bind_env(GemmBatch& g, const Env& in, const Site& Abra, const Site& Aket, size_t tsz, const Env& out);

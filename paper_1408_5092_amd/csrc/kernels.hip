@@ -9,6 +9,7 @@
 // * k_eig_tridiag: batched symmetric eigensolver (Householder tridiagonal
 //   reduction, accumulated Q, implicit QL), one workgroup per matrix.
 // * CG vector kernels with fixed-order two-pass reductions.
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <chrono>
@@ -666,38 +667,53 @@ __device__ void block_partial(double v, double* red, double* out) {
 
 inline int n_blocks(size_t n) {
     size_t b = (n + RED_THREADS - 1) / RED_THREADS;
-    if (b > (size_t)kPartials / 2) b = kPartials / 2;
+    if (b > (size_t)kPartials / 4) b = kPartials / 4;
     if (b < 1) b = 1;
     return (int)b;
 }
 
-// Thread t of block b covers elements b*RED_THREADS + t + k*(nb*RED_THREADS).
-__global__ __launch_bounds__(RED_THREADS) void k_dot_partial(const double* a, const double* b, size_t n,
-                                                             double* part) {
+// One-launch reduction of NV sums: every block writes its NV block sums to
+// part[v * kPartials / 4 + block]; the last block to arrive (counted at
+// part + kPartials) adds each row in block order, writes scal[slots[v]] and
+// resets the counter.  The order of every addition is fixed.
+template <int NV>
+__device__ void reduce_rows(const double (&v)[NV], double* part, double* scal, const int (&slots)[NV]) {
     __shared__ double red[RED_THREADS];
+    __shared__ int last;
+    constexpr int stride = kPartials / 4;
+    for (int r = 0; r < NV; ++r) {
+        block_partial(v[r], red, part + r * stride + blockIdx.x);
+        __syncthreads();
+    }
+    int* counter = reinterpret_cast<int*>(part + kPartials);
+    if (threadIdx.x == 0) {
+        __threadfence();
+        last = atomicAdd(counter, 1) == (int)gridDim.x - 1;
+    }
+    __syncthreads();
+    if (!last) return;
+    __threadfence();
+    for (int r = 0; r < NV; ++r) {
+        double sacc = 0.0;
+        for (int i = threadIdx.x; i < (int)gridDim.x; i += RED_THREADS) sacc += part[r * stride + i];
+        block_partial(sacc, red, scal + slots[r]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *counter = 0;
+}
+
+// Thread t of block b covers elements b*RED_THREADS + t + k*(nb*RED_THREADS).
+__global__ __launch_bounds__(RED_THREADS) void k_dot(const double* a, const double* b, size_t n, double* part,
+                                                     double* scal, int slot) {
     double s = 0.0;
     for (size_t e = (size_t)blockIdx.x * RED_THREADS + threadIdx.x; e < n; e += (size_t)gridDim.x * RED_THREADS)
         s += a[e] * b[e];
-    block_partial(s, red, part + blockIdx.x);
-}
-
-__global__ __launch_bounds__(RED_THREADS) void k_reduce(const double* part, int nb, int stride, double* scal,
-                                                        int slot0, int slot1) {
-    __shared__ double red[RED_THREADS];
-    double s0 = 0.0, s1 = 0.0;
-    for (int i = threadIdx.x; i < nb; i += RED_THREADS) {
-        s0 += part[i];
-        if (slot1 >= 0) s1 += part[stride + i];
-    }
-    block_partial(s0, red, scal + slot0);
-    __syncthreads();
-    if (slot1 >= 0) block_partial(s1, red, scal + slot1);
+    reduce_rows<1>({s}, part, scal, {slot});
 }
 
 __global__ __launch_bounds__(RED_THREADS) void k_cg_init(double* r, double* z, double* p, const double* b,
                                                          const double* q, const double* d, size_t n, double* part,
-                                                         int stride) {
-    __shared__ double red[RED_THREADS];
+                                                         double* scal) {
     double rz = 0.0, rr = 0.0, bb = 0.0;
     for (size_t e = (size_t)blockIdx.x * RED_THREADS + threadIdx.x; e < n; e += (size_t)gridDim.x * RED_THREADS) {
         const double rv = -b[e] - q[e];
@@ -709,31 +725,26 @@ __global__ __launch_bounds__(RED_THREADS) void k_cg_init(double* r, double* z, d
         rr += rv * rv;
         bb += b[e] * b[e];
     }
-    block_partial(rz, red, part + blockIdx.x);
-    __syncthreads();
-    block_partial(rr, red, part + stride + blockIdx.x);
-    __syncthreads();
-    block_partial(bb, red, part + 2 * stride + blockIdx.x);
+    reduce_rows<3>({rz, rr, bb}, part, scal, {(int)S_RZ0, (int)S_RR, (int)S_BB});
 }
 
 __global__ __launch_bounds__(RED_THREADS) void k_shift_dot(double* q, const double* p, double shift, size_t n,
-                                                           double* part) {
-    __shared__ double red[RED_THREADS];
+                                                           double* part, double* scal) {
     double s = 0.0;
     for (size_t e = (size_t)blockIdx.x * RED_THREADS + threadIdx.x; e < n; e += (size_t)gridDim.x * RED_THREADS) {
         const double qv = q[e] - shift * p[e];
         q[e] = qv;
         s += p[e] * qv;
     }
-    block_partial(s, red, part + blockIdx.x);
+    reduce_rows<1>({s}, part, scal, {(int)S_PQ});
 }
 
+// alpha = rz / pq (0 when pq is 0: a search direction that vanished)
 __global__ __launch_bounds__(RED_THREADS) void k_cg_update(double* x, double* r, double* z, const double* p,
                                                            const double* q, const double* d, size_t n,
-                                                           const double* scal, int rz_cur, double* part,
-                                                           int stride) {
-    __shared__ double red[RED_THREADS];
-    const double alpha = scal[rz_cur] / scal[S_PQ];
+                                                           double* scal, int rz_cur, int rz_new, double* part) {
+    const double pq = scal[S_PQ];
+    const double alpha = pq != 0.0 ? scal[rz_cur] / pq : 0.0;
     double rz = 0.0, rr = 0.0;
     for (size_t e = (size_t)blockIdx.x * RED_THREADS + threadIdx.x; e < n; e += (size_t)gridDim.x * RED_THREADS) {
         x[e] += alpha * p[e];
@@ -744,14 +755,13 @@ __global__ __launch_bounds__(RED_THREADS) void k_cg_update(double* x, double* r,
         rz += rv * zv;
         rr += rv * rv;
     }
-    block_partial(rz, red, part + blockIdx.x);
-    __syncthreads();
-    block_partial(rr, red, part + stride + blockIdx.x);
+    reduce_rows<2>({rz, rr}, part, scal, {rz_new, (int)S_RR});
 }
 
 __global__ __launch_bounds__(RED_THREADS) void k_cg_direction(double* p, const double* z, size_t n,
                                                               const double* scal, int rz_cur, int rz_new) {
-    const double beta = scal[rz_new] / scal[rz_cur];
+    const double den = scal[rz_cur];
+    const double beta = den != 0.0 ? scal[rz_new] / den : 0.0;
     for (size_t e = (size_t)blockIdx.x * RED_THREADS + threadIdx.x; e < n; e += (size_t)gridDim.x * RED_THREADS)
         p[e] = z[e] + beta * p[e];
 }
@@ -874,6 +884,28 @@ void zero(void* p, size_t bytes) {
     check(hipMemsetAsync(p, 0, bytes, g_stream), "hipMemsetAsync");
 }
 void sync() { check(hipStreamSynchronize(g_stream), "hipStreamSynchronize"); }
+void* host_alloc(size_t bytes) {
+    void* p = nullptr;
+    check(hipHostMalloc(&p, bytes, hipHostMallocDefault), "hipHostMalloc");
+    return p;
+}
+void host_free(void* p) {
+    if (p) (void)hipHostFree(p);
+}
+void d2h_async(void* dst, const void* src, size_t bytes) {
+    if (!bytes) return;
+    check(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, g_stream), "hipMemcpyAsync D2H");
+}
+void* event_create() {
+    hipEvent_t e;
+    check(hipEventCreateWithFlags(&e, hipEventDisableTiming), "hipEventCreate");
+    return e;
+}
+void event_destroy(void* e) {
+    if (e) (void)hipEventDestroy(static_cast<hipEvent_t>(e));
+}
+void event_record(void* e) { check(hipEventRecord(static_cast<hipEvent_t>(e), g_stream), "hipEventRecord"); }
+void event_wait(void* e) { check(hipEventSynchronize(static_cast<hipEvent_t>(e)), "hipEventSynchronize"); }
 double now() {
     using namespace std::chrono;
     return duration<double>(steady_clock::now().time_since_epoch()).count();
@@ -919,28 +951,32 @@ void prof_flush() {
     g_pending.clear();
 }
 
-// Records events around one launch when profiling is on.
-struct Prof {
-    ProfRec r;
-    bool on;
-    Prof(int kind, double flops, double bytes) : on(g_prof) {
-        if (!on) return;
-        r = {kind, take_event(), take_event(), flops, bytes};
-        check(hipEventRecord(r.a, g_stream), "hipEventRecord");
-    }
-    ~Prof() noexcept(false) {
-        if (!on) return;
-        check(hipEventRecord(r.b, g_stream), "hipEventRecord");
+// Launches on the library stream.  While recording, the launch goes through
+// hipExtLaunchKernelGGL with a pair of events that take the dispatch's own
+// start and end times, so the recorded durations are kernel execution only.
+template <typename F, typename... Args>
+void launch(int kind, double flops, double bytes, F kernel, dim3 grid, dim3 block, size_t shm, Args... args) {
+    if (g_prof) {
+        ProfRec r{kind, take_event(), take_event(), flops, bytes};
+        hipExtLaunchKernelGGL(kernel, grid, block, (uint32_t)shm, g_stream, r.a, r.b, 0, args...);
         g_pending.push_back(r);
         if (g_pending.size() >= 4096) prof_flush();
+    } else {
+        hipLaunchKernelGGL(kernel, grid, block, shm, g_stream, args...);
     }
-};
+}
 }  // namespace
+
+// Empty kernel launched whenever recording starts or stops, so that an
+// external kernel trace can find the recorded window.
+__global__ void k_profile_mark(int on) {}
 
 void profile_enable(bool on) {
     if (g_prof) prof_flush();
     g_prof = on;
     for (auto& s : g_stats) s = KernelStats();
+    hipLaunchKernelGGL(k_profile_mark, dim3(1), dim3(64), 0, g_stream, on ? 1 : 0);
+    check(hipGetLastError(), "k_profile_mark");
 }
 
 KernelStats profile_stats(int kind) {
@@ -952,39 +988,35 @@ KernelStats profile_stats(int kind) {
 void gemm_grouped(const Bases& b, const GemmGroup* groups, int ngroups, const GemmTerm* terms, int ntiles,
                   double flops, double bytes) {
     if (ntiles <= 0) return;
-    Prof p(K_GEMM, flops, bytes);
-    hipLaunchKernelGGL(k_gemm_grouped, dim3((ntiles + 3) / 4), dim3(256), 0, g_stream, b, groups, ngroups, terms, ntiles);
+    launch(K_GEMM, flops, bytes, k_gemm_grouped, dim3((ntiles + 3) / 4), dim3(256), 0, b, groups, ngroups, terms,
+           ntiles);
     check(hipGetLastError(), "k_gemm_grouped");
 }
 void axpy_grouped(const Bases& b, const AxpyGroup* groups, int ngroups, const AxpyTerm* terms, double flops,
                   double bytes) {
     if (ngroups <= 0) return;
-    Prof p(K_AXPY, flops, bytes);
-    hipLaunchKernelGGL(k_axpy_grouped, dim3(ngroups), dim3(256), 0, g_stream, b, groups, terms);
+    launch(K_AXPY, flops, bytes, k_axpy_grouped, dim3(ngroups), dim3(256), 0, b, groups, terms);
     check(hipGetLastError(), "k_axpy_grouped");
 }
 void diag_grouped(const Bases& b, const DiagGroup* groups, int ngroups, const DiagTerm* terms) {
     if (ngroups <= 0) return;
-    Prof p(K_DIAG, 0, 0);
-    hipLaunchKernelGGL(k_diag_grouped, dim3(ngroups), dim3(256), 0, g_stream, b, groups, terms);
+    launch(K_DIAG, 0, 0, k_diag_grouped, dim3(ngroups), dim3(256), 0, b, groups, terms);
     check(hipGetLastError(), "k_diag_grouped");
 }
 void eig_reduce(const EigJob* jobs, int njobs, int nmax) {
     if (njobs <= 0) return;
     if (nmax > EIG_MAXN) throw Error{MPSPT_E_ARG, "eigensolver limited to n <= 512"};
-    Prof p(K_EIG, 0, 0);
     if (eig_reduce_class(nmax) == 0) {
         const size_t shm = (size_t)nmax * (nmax + 1) * sizeof(double);
-        hipLaunchKernelGGL(k_eig_reduce<true>, dim3(njobs), dim3(1024), shm, g_stream, jobs);
+        launch(K_EIG, 0, 0, k_eig_reduce<true>, dim3(njobs), dim3(1024), shm, jobs);
     } else {
-        hipLaunchKernelGGL(k_eig_reduce<false>, dim3(njobs), dim3(1024), 0, g_stream, jobs);
+        launch(K_EIG, 0, 0, k_eig_reduce<false>, dim3(njobs), dim3(1024), 0, jobs);
     }
     check(hipGetLastError(), "k_eig_reduce");
 }
 void eig_vectors(const EigJob* jobs, int njobs, int nmax, int kmax, int* status) {
     if (njobs <= 0) return;
     if (nmax > EIG_MAXN || kmax > nmax) throw Error{MPSPT_E_ARG, "eigensolver limited to k <= n <= 512"};
-    Prof p(K_EIGV, 0, 0);
     const size_t words = g_lds_budget / sizeof(double);
     const size_t uw = (size_t)3 * nmax * kmax;  // solve rows, aliasing the later phases' LDS
     if (eig_vectors_class(nmax, kmax) == 0) {
@@ -992,14 +1024,14 @@ void eig_vectors(const EigJob* jobs, int njobs, int nmax, int kmax, int* status)
         const size_t need = eigv_lds_words(nmax, kmax, 16, true);
         const int u_lds = base + uw <= words ? 1 : 0;
         const size_t shm = std::max(need, u_lds ? base + uw : 0) * sizeof(double);
-        hipLaunchKernelGGL(k_eig_vectors<true>, dim3(njobs), dim3(1024), shm, g_stream, jobs, status, 16, u_lds);
+        launch(K_EIGV, 0, 0, k_eig_vectors<true>, dim3(njobs), dim3(1024), shm, jobs, status, 16, u_lds);
     } else {
         int rb = 16;
         while (rb > 1 && eigv_lds_words(nmax, kmax, rb, false) > words) --rb;
         const size_t need = eigv_lds_words(nmax, kmax, rb, false);
         const int u_lds = uw <= words ? 1 : 0;
         const size_t shm = std::max(need, u_lds ? uw : 0) * sizeof(double);
-        hipLaunchKernelGGL(k_eig_vectors<false>, dim3(njobs), dim3(1024), shm, g_stream, jobs, status, rb, u_lds);
+        launch(K_EIGV, 0, 0, k_eig_vectors<false>, dim3(njobs), dim3(1024), shm, jobs, status, rb, u_lds);
     }
     check(hipGetLastError(), "k_eig_vectors");
 }
@@ -1008,60 +1040,43 @@ int eig_vectors_class(int n, int k) { return eigv_lds_words(n, k, 16, true) * si
 size_t eig_work(int n) { return 2 * (size_t)n + 4 * (size_t)n * n; }
 
 void dot(const double* a, const double* b, size_t n, double* scal, int slot, double* partials) {
-    Prof pr(K_VEC, 2.0 * n, 16.0 * n);
     const int nb = n_blocks(n);
-    hipLaunchKernelGGL(k_dot_partial, dim3(nb), dim3(RED_THREADS), 0, g_stream, a, b, n, partials);
-    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(RED_THREADS), 0, g_stream, partials, nb, 0, scal, slot, -1);
+    launch(K_VEC, 2.0 * n, 16.0 * n, k_dot, dim3(nb), dim3(RED_THREADS), 0, a, b, n, partials, scal, slot);
     check(hipGetLastError(), "dot");
 }
 void cg_init(double* r, double* z, double* p, const double* b, const double* q, const double* d, size_t n,
              double* scal, double* partials) {
-    const int nb = std::min(n_blocks(n), kPartials / 3);
-    Prof pr(K_VEC, 6.0 * n, 48.0 * n);
-    const int stride = kPartials / 3;
-    hipLaunchKernelGGL(k_cg_init, dim3(nb), dim3(RED_THREADS), 0, g_stream, r, z, p, b, q, d, n, partials, stride);
-    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(RED_THREADS), 0, g_stream, partials, nb, stride, scal, (int)S_RZ0,
-                       (int)S_RR);
-    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(RED_THREADS), 0, g_stream, partials + 2 * stride, nb, 0, scal,
-                       (int)S_BB, -1);
+    const int nb = n_blocks(n);
+    launch(K_VEC, 6.0 * n, 48.0 * n, k_cg_init, dim3(nb), dim3(RED_THREADS), 0, r, z, p, b, q, d, n, partials, scal);
     check(hipGetLastError(), "cg_init");
 }
 void cg_shift_dot(double* q, const double* p, double shift, size_t n, double* scal, double* partials) {
-    Prof pr(K_VEC, 4.0 * n, 24.0 * n);
     const int nb = n_blocks(n);
-    hipLaunchKernelGGL(k_shift_dot, dim3(nb), dim3(RED_THREADS), 0, g_stream, q, p, shift, n, partials);
-    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(RED_THREADS), 0, g_stream, partials, nb, 0, scal, (int)S_PQ, -1);
+    launch(K_VEC, 4.0 * n, 24.0 * n, k_shift_dot, dim3(nb), dim3(RED_THREADS), 0, q, p, shift, n, partials, scal);
     check(hipGetLastError(), "cg_shift_dot");
 }
 void cg_update(double* x, double* r, double* z, const double* p, const double* q, const double* d, size_t n,
                double* scal, int rz_cur, int rz_new, double* partials) {
-    Prof pr(K_VEC, 9.0 * n, 64.0 * n);
     const int nb = n_blocks(n);
-    const int stride = kPartials / 2;
-    hipLaunchKernelGGL(k_cg_update, dim3(nb), dim3(RED_THREADS), 0, g_stream, x, r, z, p, q, d, n, scal, rz_cur,
-                       partials, stride);
-    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(RED_THREADS), 0, g_stream, partials, nb, stride, scal, rz_new,
-                       (int)S_RR);
+    launch(K_VEC, 9.0 * n, 64.0 * n, k_cg_update, dim3(nb), dim3(RED_THREADS), 0, x, r, z, p, q, d, n, scal, rz_cur,
+           rz_new, partials);
     check(hipGetLastError(), "cg_update");
 }
 void cg_direction(double* p, const double* z, size_t n, const double* scal, int rz_cur, int rz_new) {
-    Prof pr(K_VEC, 2.0 * n, 24.0 * n);
     const int nb = n_blocks(n);
-    hipLaunchKernelGGL(k_cg_direction, dim3(nb), dim3(RED_THREADS), 0, g_stream, p, z, n, scal, rz_cur, rz_new);
+    launch(K_VEC, 2.0 * n, 24.0 * n, k_cg_direction, dim3(nb), dim3(RED_THREADS), 0, p, z, n, scal, rz_cur, rz_new);
     check(hipGetLastError(), "cg_direction");
 }
 void davidson_precond(double* t, const double* r, const double* d, double theta, size_t n) {
     if (!n) return;
-    Prof pr(K_VEC, 3.0 * n, 24.0 * n);
     const int nb = n_blocks(n);
-    hipLaunchKernelGGL(k_dav_precond, dim3(nb), dim3(RED_THREADS), 0, g_stream, t, r, d, theta, n);
+    launch(K_VEC, 3.0 * n, 24.0 * n, k_dav_precond, dim3(nb), dim3(RED_THREADS), 0, t, r, d, theta, n);
     check(hipGetLastError(), "davidson_precond");
 }
 void axpby(double* y, const double* x, double a, double b, size_t n) {
     if (!n) return;
-    Prof pr(K_VEC, 3.0 * n, 24.0 * n);
     const int nb = n_blocks(n);
-    hipLaunchKernelGGL(k_axpby, dim3(nb), dim3(RED_THREADS), 0, g_stream, y, x, a, b, n);
+    launch(K_VEC, 3.0 * n, 24.0 * n, k_axpby, dim3(nb), dim3(RED_THREADS), 0, y, x, a, b, n);
     check(hipGetLastError(), "axpby");
 }
 

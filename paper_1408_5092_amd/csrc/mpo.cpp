@@ -244,6 +244,7 @@ MPO build_mpo(OpKind kind, int k_a, int k_v, const std::vector<double>& h, const
                     c = H(p, q);
                     break;
                 case OpKind::VFull:
+                case OpKind::VPsi1:
                 case OpKind::VPsi0:
                     if (aa) break;
                     if (kind == OpKind::VPsi0 && !act(q)) break;
@@ -269,6 +270,11 @@ MPO build_mpo(OpKind kind, int k_a, int k_v, const std::vector<double>& h, const
                         case OpKind::H0:
                         case OpKind::HAct: keep = all_act; break;
                         case OpKind::VFull: keep = !all_act; break;
+                        case OpKind::VPsi1: {
+                            const int dnv = !act(p) + !act(r) - !act(s) - !act(q);
+                            keep = !all_act && dnv >= -1 && dnv <= 1;
+                            break;
+                        }
                         case OpKind::VPsi0: keep = !all_act && act(q) && act(s); break;
                     }
                     if (!keep) continue;

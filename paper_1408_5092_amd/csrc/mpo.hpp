@@ -33,7 +33,11 @@ struct MPO {
     std::vector<std::vector<MPOEntry>> W;   // per site
 };
 
-enum class OpKind { H0, VPsi0, VFull, HAct };
+// H0: Dyall H0; VPsi0: the terms of V = H - H0 that act on Psi0 (annihilators
+// active); VFull: all of V; VPsi1: the terms of V that connect states with one
+// or two virtual electrons (the number of virtual electrons changes by at most
+// one), enough for <Psi1|V|Psi1>; HAct: H on the active sites alone.
+enum class OpKind { H0, VPsi0, VFull, HAct, VPsi1 };
 
 // Integrals of the whole orbital space (k = k_a + k_v): h[k*k], eri[k^4].
 // HAct builds the active-space Hamiltonian on k_a sites only.

@@ -65,6 +65,12 @@ def test_library_mpo_matches_determinant_operator(lib, ka, kv, seed):
     empty = np.zeros(4 ** k, dtype=bool)
     empty[perm[fock.n_virtual(basis, ka) == 0]] = True
     assert np.abs(D1[:, empty] - dense["V"][:, empty]).max() < 1e-13
+    # the part of V used for E3 equals V between states with one or two virtual electrons
+    D3 = mpspt.mpo_dense(ka, kv, ints.h, eri, ints.eps_virt, 3, lib=lib)
+    psi1 = np.zeros(4 ** k, dtype=bool)
+    nv = fock.n_virtual(basis, ka)
+    psi1[perm[(nv == 1) | (nv == 2)]] = True
+    assert np.abs(D3[np.ix_(psi1, psi1)] - dense["V"][np.ix_(psi1, psi1)]).max() < 1e-13
 
 
 def test_mpo_channel_counts_scale_as_paper(lib):
