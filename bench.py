@@ -18,6 +18,7 @@ layout is described in the design notes, not run.
 import argparse
 import json
 import os
+import re
 import statistics
 import sys
 import time
@@ -29,6 +30,33 @@ METRIC = "MPS-PT E2 time-to-1µEh (s) & sigma-build TFLOP/s, batched-FP32 vs pla
 K_A, K_V, N_ELEC, RANK, M0, M1, SWEEPS, SEED = 8, 16, 8, 32, 64, 128, 4, 0
 PEAK_HBM_GBS = 8000.0
 PEAK_FP64_TFLOPS = 78.6
+
+
+def kernel_digest(name):
+    """sha256 of a kernel's source text in kernels.hip (signature through the closing brace)."""
+    import hashlib
+    src = open(os.path.join(ROOT, "paper_1408_5092_amd", "csrc", "kernels.hip")).read()
+    i = src.index(f"void {name}(")
+    i = src.rfind("\n", 0, i) + 1
+    k, depth = src.index("{", i), 0
+    while True:
+        depth += {"{": 1, "}": -1}.get(src[k], 0)
+        if depth == 0:
+            break
+        k += 1
+    return hashlib.sha256(src[i:k + 1].encode()).hexdigest()
+
+
+def measured_traffic(kernel):
+    """HBM bytes per dispatch from the committed counter runs in profiles/, or None when the
+    kernel's source changed since they were taken (or none were taken for it)."""
+    import glob
+    for path in glob.glob(os.path.join(ROOT, "profiles", "*.md")):
+        fields = dict(re.findall(r"^(traffic_kernel|traffic_bytes_per_dispatch|kernel_source_sha256): (\S+)$",
+                                 open(path).read(), re.M))
+        if fields.get("traffic_kernel") == kernel and fields.get("kernel_source_sha256") == kernel_digest(kernel):
+            return float(fields["traffic_bytes_per_dispatch"])
+    return None
 
 
 def time_to_tol(trace_e2, trace_t, e_ref, tol=1e-6):
@@ -191,7 +219,7 @@ def main():
         "kernel_seconds": {s["kernel"]: s["seconds"] for s in stats.values()},
         "roofline": {
             "kernel": dom["kernel"], "bound": bound, "achieved": achieved, "peak": peak, "unit": unit,
-            "frac": achieved / peak, "traffic": None,
+            "frac": achieved / peak, "traffic": measured_traffic(dom["kernel"]),
             "avg_launch_us": avg * 1e6, "launches": dom["launches"],
             "alg_flops_per_launch": flops_per, "alg_bytes_per_launch": bytes_per,
             "alg_intensity_flop_per_byte": intensity,
