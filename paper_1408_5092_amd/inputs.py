@@ -187,3 +187,15 @@ WORKLOADS = {
     "c1_4a4v": dict(k_a=4, k_v=4, n_elec=4, rank=16, M0=None, M1=16, sweeps=None),
     "c2_8a16v": dict(k_a=8, k_v=16, n_elec=8, rank=32, M0=64, M1=128, sweeps=4),
 }
+
+
+def mlp_init(seed: int, n_in: int = 8, n_hidden: int = 64) -> np.ndarray:
+    """Seeded initial parameters of the preconditioner network, flat float32 in the
+    layout W1[h][f], b1[h], W2[h][h], b2[h], w3[h], b3: weights N(0, 1/fan_in),
+    biases 0, output bias 0.5413 (softplus(0.5413) = 1, the Jacobi scale)."""
+    rng = np.random.default_rng(seed)
+    W1 = rng.normal(0.0, 1.0 / np.sqrt(n_in), (n_hidden, n_in))
+    W2 = rng.normal(0.0, 1.0 / np.sqrt(n_hidden), (n_hidden, n_hidden))
+    w3 = rng.normal(0.0, 0.1 / np.sqrt(n_hidden), n_hidden)
+    parts = [W1.ravel(), np.zeros(n_hidden), W2.ravel(), np.zeros(n_hidden), w3, [0.5413248546129181]]
+    return np.concatenate(parts).astype(np.float32)
