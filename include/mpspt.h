@@ -104,6 +104,7 @@ typedef struct {
     double cg_rel_tol;    /* local solve stops when |A x + b| <= cg_rel_tol |b| */
     int32_t cg_max_iter;  /* cap on CG iterations per local solve */
     int32_t compute_e3;   /* 1: evaluate E3 on the final state */
+    int32_t precond;      /* 0: Jacobi; 1: learned block scaling (mpspt_precond_set first) */
 } mpspt_sweep_params;
 
 typedef struct {
@@ -128,8 +129,42 @@ typedef struct {
 } mpspt_result;
 
 /* Run the sweep.  Errors: MPSPT_E_STATE if integrals, partition, Psi0 or the
- * Psi1 guess are missing; MPSPT_E_INDEFINITE if CG meets p.Ap <= 0. */
+ * Psi1 guess are missing (or precond = 1 without a network); MPSPT_E_ARG for
+ * precond = 1 while harvesting; MPSPT_E_INDEFINITE if CG meets p.Ap <= 0. */
 mpspt_status mpspt_sweep(mpspt_ctx *ctx, const mpspt_sweep_params *params, mpspt_result *out);
+
+/* Learned CG preconditioner.  With precond = 1 each block B of the two-site
+ * tensor is preconditioned by s_B / diag(H0_eff - E0) instead of the Jacobi
+ * 1 / diag; s_B > 0 comes from a network 8 -> 64 -> 64 -> 1 (tanh, tanh,
+ * softplus) of block features (mean, spread, extremes of log diag, log block
+ * dims, log of the block's share of the initial CG residual, window
+ * position), evaluated once per local solve after the first residual.  A positive block
+ * scaling keeps the preconditioner SPD, so converged energies do not depend
+ * on it (only CG iteration counts do).  The paper solves the local equation
+ * by conjugate gradients and says nothing about the preconditioner; these
+ * calls are for callers that train and use one.
+ * Parameters: MPSPT_MLP_PARAMS floats, layout W1[64][8], b1[64], W2[64][64],
+ * b2[64], w3[64], b3; mpspt_precond_set copies them to the device and resets
+ * the Adam state.  mpspt_mlp_grad: loss (1/n) sum (log s - log t)^2 and its
+ * gradient for n samples X[n][8] with targets t > 0, parameters unchanged.
+ * mpspt_mlp_train_step: the same loss, then one Adam step (beta 0.9 / 0.999,
+ * eps 1e-8) with rate lr on the device parameters.  mpspt_harvest(1) clears
+ * and starts collecting, during later sweeps (Jacobi only), one sample per
+ * block of every local solve: its features and the target
+ * <e0_B, z_B> / <z_B, z_B> (z = r0 / diag with r0 the initial residual,
+ * e0 = x - x0 the initial error of the converged solve), kept when positive
+ * and clipped to [0.05, 20]; mpspt_harvest_get returns them (n_out alone
+ * when cap = 0). */
+#define MPSPT_MLP_PARAMS 4801
+#define MPSPT_MLP_INPUTS 8
+mpspt_status mpspt_precond_set(mpspt_ctx *ctx, const float *params, int32_t n);
+mpspt_status mpspt_precond_get(mpspt_ctx *ctx, float *params, int32_t n);
+mpspt_status mpspt_mlp_grad(mpspt_ctx *ctx, const float *X, const float *t, int32_t n, float *grad,
+                            float *loss);
+mpspt_status mpspt_mlp_train_step(mpspt_ctx *ctx, const float *X, const float *t, int32_t n, float lr,
+                                  float *loss);
+mpspt_status mpspt_harvest(mpspt_ctx *ctx, int32_t enable);
+mpspt_status mpspt_harvest_get(mpspt_ctx *ctx, int64_t cap, float *X, float *t, int64_t *n_out);
 
 /* Kernel timing: enable = 1 starts recording HIP events around every launch
  * on the context's stream (counters reset), 0 stops.  mpspt_kernel_stats

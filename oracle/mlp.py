@@ -19,12 +19,15 @@ Flat parameter layout (N_PARAMS = 4801): W1[64][8] row major, b1[64],
 W2[64][64] row major, b2[64], w3[64], b3.
 Adam: beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected moments.
 
-Features of a block B with diagonal values d (all > 0), right-hand side b
-and the window's whole right-hand side b_all, window i of n - 1:
+CG starts from the previous window's state x0, so the preconditioner's job is
+to map the initial residual r0 = -b - A x0 onto the initial error
+e0 = x - x0 (A e0 = r0).  Features of a block B with diagonal values d
+(all > 0), initial residual r0 and the window's whole initial residual r_all,
+window i of n - 1:
   mean log d, std log d, min log d - mean, max log d - mean, log rows,
-  log cols, log(|b_B| / |b_all|) (with |.| floored at 1e-300), i / (n - 2).
-Target of B from the converged solution x: with z = -b / d (the Jacobi
-step), t = <x_B, z_B> / <z_B, z_B>, the scale that best fits x_B by z_B.
+  log cols, log(|r0_B| / |r_all|) (norms floored at 1e-300), i / (n - 2).
+Target of B from the converged solution: with z = r0 / d (the Jacobi step),
+t = <e0_B, z_B> / <z_B, z_B>, the scale that best fits e0_B by z_B.
 """
 import numpy as np
 
@@ -96,16 +99,16 @@ def adam_step(p, m, v, g, step, lr, beta1=0.9, beta2=0.999, eps=1e-8):
     return p - lr * mh / (np.sqrt(vh) + eps), m, v
 
 
-def block_features(d, b, b_all_norm, window, n_sites):
-    """Features of one block (d, b: the block's diagonal and right-hand side, 2-D)."""
+def block_features(d, r0, r_all_norm, window, n_sites):
+    """Features of one block (d, r0: the block's diagonal and initial residual, 2-D)."""
     ld = np.log(d.ravel())
     mu = ld.mean()
-    bn = max(np.linalg.norm(b), 1e-300)
+    rn = max(np.linalg.norm(r0), 1e-300)
     return np.array([mu, ld.std(), ld.min() - mu, ld.max() - mu, np.log(d.shape[0]), np.log(d.shape[1]),
-                     np.log(bn / max(b_all_norm, 1e-300)), window / (n_sites - 2)])
+                     np.log(rn / max(r_all_norm, 1e-300)), window / (n_sites - 2)])
 
 
-def block_target(d, b, x):
-    z = -b / d
+def block_target(d, r0, e0):
+    z = r0 / d
     zz = float(np.sum(z * z))
-    return float(np.sum(x * z)) / zz if zz > 0 else None
+    return float(np.sum(e0 * z)) / zz if zz > 0 else None

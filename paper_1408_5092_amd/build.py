@@ -9,7 +9,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libmpspt.so")
-SOURCES = ["kernels.hip", "engine.cpp", "mpo.cpp", "capi.cpp"]
+SOURCES = ["kernels.hip", "precond.hip", "engine.cpp", "mpo.cpp", "capi.cpp"]
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-Wall", "-Wno-unused-function"]

@@ -209,6 +209,7 @@ mpspt_status mpspt_sweep(mpspt_ctx* ctx, const mpspt_sweep_params* params, mpspt
         p.cg_rel_tol = params->cg_rel_tol > 0 ? params->cg_rel_tol : 1e-10;
         p.cg_max_iter = params->cg_max_iter > 0 ? params->cg_max_iter : 500;
         p.compute_e3 = params->compute_e3;
+        p.precond = params->precond;
         if (p.n_sweeps > 64 || p.n_sweeps < 0) throw argerr("n_sweeps must be in [0, 64]");
         mpspt::SweepResult r = ctx->eng.sweep(p);
         std::memset(out, 0, sizeof(*out));
@@ -234,6 +235,49 @@ mpspt_status mpspt_sweep(mpspt_ctx* ctx, const mpspt_sweep_params* params, mpspt
 mpspt_status mpspt_profile(mpspt_ctx* ctx, int32_t enable) {
     if (!ctx) return MPSPT_E_ARG;
     return guard(ctx, [&] { mpspt::dev::profile_enable(enable != 0); });
+}
+
+mpspt_status mpspt_precond_set(mpspt_ctx* ctx, const float* params, int32_t n) {
+    if (!ctx || !params) return MPSPT_E_ARG;
+    return guard(ctx, [&] { ctx->eng.precond_set(params, n); });
+}
+
+mpspt_status mpspt_precond_get(mpspt_ctx* ctx, float* params, int32_t n) {
+    if (!ctx || !params) return MPSPT_E_ARG;
+    return guard(ctx, [&] { ctx->eng.precond_get(params, n); });
+}
+
+mpspt_status mpspt_mlp_grad(mpspt_ctx* ctx, const float* X, const float* t, int32_t n, float* grad, float* loss) {
+    if (!ctx || !X || !t || !loss) return MPSPT_E_ARG;
+    return guard(ctx, [&] { *loss = ctx->eng.mlp_step(X, t, n, 0.0f, false, grad); });
+}
+
+mpspt_status mpspt_mlp_train_step(mpspt_ctx* ctx, const float* X, const float* t, int32_t n, float lr,
+                                  float* loss) {
+    if (!ctx || !X || !t) return MPSPT_E_ARG;
+    if (!(lr > 0.0f)) return MPSPT_E_ARG;
+    return guard(ctx, [&] {
+        const float l = ctx->eng.mlp_step(X, t, n, lr, true, nullptr);
+        if (loss) *loss = l;
+    });
+}
+
+mpspt_status mpspt_harvest(mpspt_ctx* ctx, int32_t enable) {
+    if (!ctx) return MPSPT_E_ARG;
+    return guard(ctx, [&] { ctx->eng.set_harvest(enable != 0); });
+}
+
+mpspt_status mpspt_harvest_get(mpspt_ctx* ctx, int64_t cap, float* X, float* t, int64_t* n_out) {
+    if (!ctx || !n_out) return MPSPT_E_ARG;
+    return guard(ctx, [&] {
+        const auto& hx = ctx->eng.harvest_X();
+        const auto& ht = ctx->eng.harvest_t();
+        *n_out = (int64_t)ht.size();
+        if (cap <= 0) return;
+        if (!X || !t || cap < (int64_t)ht.size()) throw argerr("output smaller than the harvested sample count");
+        std::copy(hx.begin(), hx.end(), X);
+        std::copy(ht.begin(), ht.end(), t);
+    });
 }
 
 mpspt_status mpspt_kernel_stats(mpspt_ctx* ctx, int32_t kind, double* seconds, int64_t* launches, double* flops,

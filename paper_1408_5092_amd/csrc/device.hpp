@@ -157,6 +157,28 @@ void axpby(double* y, const double* x, double a, double b, size_t n);
 // t = r / (theta - d), with |theta - d| floored at 1e-8 (Davidson correction)
 void davidson_precond(double* t, const double* r, const double* d, double theta, size_t n);
 
+// Learned preconditioner (precond.hip).  A block of a two-site vector:
+// offset (doubles), leading dimension, rows, columns.
+struct BlockRef {
+    int64_t off;
+    int32_t ld, m, n;
+};
+constexpr int kMlpIn = 8, kMlpHidden = 64;
+constexpr int kMlpParams = kMlpHidden * kMlpIn + kMlpHidden + kMlpHidden * kMlpHidden + 2 * kMlpHidden + 1;
+constexpr int kBlockStats = 8;  // per block: sum log d, sum (log d)^2, |r|^2, z.e, z.z, min / max log d, count
+// stats[nb][kBlockStats] of d, r and (if e is not null) e, with z = r / d
+void block_stats(const BlockRef* blocks, int nb, const double* d, const double* r, const double* e, double* stats);
+// features feat[nb][kMlpIn] (if not null) and network scales scale[nb]
+void precond_scales(const double* stats, const BlockRef* blocks, int nb, float site_frac, const float* params,
+                    float* feat, float* scale);
+// d <- d / scale on every element of each block
+void scale_blocks(const BlockRef* blocks, int nb, const float* scale, double* d);
+// Loss (and gradient into grad, if not null) of the network over n samples,
+// then one Adam step when update is set (step counts from 1).
+void mlp_train(const float* X, const float* t, int n, float* params, float* m, float* v, float* grad, float* loss,
+               int step, float lr, bool update, float* scratch);
+size_t mlp_scratch_floats(int n);
+
 constexpr int kPartials = 512;        // block sums: four rows of kPartials / 4
 constexpr int kPartialsWords = 520;   // with the arrival counter after them
 

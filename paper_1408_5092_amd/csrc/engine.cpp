@@ -486,6 +486,113 @@ void Engine::set_partition(std::vector<double> eps) {
     have_psi0 = have_psi1 = false;
 }
 
+// ------------------------------------------------- learned preconditioner
+void Engine::precond_set(const float* p, int n) {
+    if (n != dev::kMlpParams) throw err(MPSPT_E_ARG, "the network has " + std::to_string(dev::kMlpParams) + " parameters");
+    for (int k = 0; k < n; ++k)
+        if (!std::isfinite(p[k])) throw err(MPSPT_E_ARG, "non-finite network parameter");
+    const size_t words = (dev::kMlpParams + 1) / 2;
+    for (DevBuf* b : {&mlp_, &mlp_m_, &mlp_v_}) b->ensure(words);
+    dev::h2d(mlp_.p, p, n * sizeof(float));
+    dev::zero(mlp_m_.p, words * sizeof(double));
+    dev::zero(mlp_v_.p, words * sizeof(double));
+    dev::sync();
+    mlp_step_ = 0;
+    mlp_set_ = true;
+}
+
+void Engine::precond_get(float* p, int n) const {
+    if (!mlp_set_) throw err(MPSPT_E_STATE, "no preconditioner network loaded");
+    if (n < dev::kMlpParams) throw err(MPSPT_E_ARG, "output too small for the network parameters");
+    dev::d2h(p, mlp_.p, dev::kMlpParams * sizeof(float));
+}
+
+float Engine::mlp_step(const float* X, const float* t, int n, float lr, bool update, float* grad) {
+    if (!mlp_set_) throw err(MPSPT_E_STATE, "no preconditioner network loaded");
+    if (n <= 0) throw err(MPSPT_E_ARG, "training batch is empty");
+    for (int k = 0; k < n; ++k)
+        if (!(t[k] > 0.0f) || !std::isfinite(t[k])) throw err(MPSPT_E_ARG, "targets must be positive and finite");
+    for (size_t k = 0; k < (size_t)n * dev::kMlpIn; ++k)
+        if (!std::isfinite(X[k])) throw err(MPSPT_E_ARG, "non-finite feature");
+    // io: X (n * in), t (n), grad (params), loss (1)
+    const size_t fl = (size_t)n * dev::kMlpIn + n + dev::kMlpParams + 2;
+    mlp_io_.ensure((fl + 1) / 2);
+    float* io = reinterpret_cast<float*>(mlp_io_.p);
+    float *dX = io, *dt = io + (size_t)n * dev::kMlpIn, *dg = dt + n, *dl = dg + dev::kMlpParams;
+    dev::h2d(dX, X, (size_t)n * dev::kMlpIn * sizeof(float));
+    dev::h2d(dt, t, (size_t)n * sizeof(float));
+    mlp_scr_.ensure((dev::mlp_scratch_floats(n) + 1) / 2);
+    if (update) ++mlp_step_;
+    dev::mlp_train(dX, dt, n, reinterpret_cast<float*>(mlp_.p), reinterpret_cast<float*>(mlp_m_.p),
+                   reinterpret_cast<float*>(mlp_v_.p), grad ? dg : nullptr, dl, mlp_step_, lr, update,
+                   reinterpret_cast<float*>(mlp_scr_.p));
+    float loss = 0.0f;
+    dev::d2h(&loss, dl, sizeof(float));
+    if (grad) dev::d2h(grad, dg, dev::kMlpParams * sizeof(float));
+    return loss;
+}
+
+void Engine::set_harvest(bool on) {
+    harvest_ = on;
+    hx_.clear();
+    ht_.clear();
+}
+
+int Engine::precond_blocks(const Two& lay) {
+    std::vector<dev::BlockRef> br;
+    br.reserve(lay.blk.size());
+    for (size_t bb = 0; bb < lay.blk.size(); ++bb) {
+        const auto& Y = lay.blk[bb];
+        if (Y.rows > 0 && Y.cols > 0) br.push_back({(int64_t)lay.off((int)bb), lay.ld((int)bb), Y.rows, Y.cols});
+    }
+    pblocks_.upload(br);
+    const int nb = (int)br.size();
+    pstats_.ensure(std::max<size_t>((size_t)nb * dev::kBlockStats, 1));
+    pfeat_.ensure(std::max<size_t>(((size_t)nb * dev::kMlpIn + 1) / 2, 1));
+    pscale_.ensure(std::max<size_t>(((size_t)nb + 1) / 2, 1));
+    return nb;
+}
+
+// d <- d / s_B with s_B from the network (the block-scaled Jacobi preconditioner)
+void Engine::precond_apply(int i, int nb) {
+    const float frac = n_ > 2 ? (float)i / (float)(n_ - 2) : 0.0f;
+    dev::block_stats(pblocks_.p, nb, d_.p, r_.p, nullptr, pstats_.p);
+    dev::precond_scales(pstats_.p, pblocks_.p, nb, frac, reinterpret_cast<const float*>(mlp_.p), nullptr,
+                        reinterpret_cast<float*>(pscale_.p));
+    dev::scale_blocks(pblocks_.p, nb, reinterpret_cast<const float*>(pscale_.p), d_.p);
+}
+
+// Features and targets of the window's blocks from the converged solution:
+// t_B = <e0_B, z_B> / <z_B, z_B> with z = r0 / d (the Jacobi step of the
+// initial residual) and e0 = x - x0 (the initial error), kept when positive
+// (clipped to [0.05, 20]).
+void Engine::harvest_window(int i, int nb) {
+    if (nb <= 0) return;
+    const float frac = n_ > 2 ? (float)i / (float)(n_ - 2) : 0.0f;
+    const size_t words = (dev::kMlpParams + 1) / 2;
+    if (!mlp_set_) {  // features do not depend on the parameters; give the kernel zeros
+        mlp_.ensure(words);
+        dev::zero(mlp_.p, words * sizeof(double));
+    }
+    const size_t n = xlay_.size;
+    dev::axpby(px0_.p, x_.p, 1.0, -1.0, n);  // e0 = x - x0
+    dev::block_stats(pblocks_.p, nb, d_.p, pr0_.p, px0_.p, pstats_.p);
+    dev::precond_scales(pstats_.p, pblocks_.p, nb, frac, reinterpret_cast<const float*>(mlp_.p),
+                        reinterpret_cast<float*>(pfeat_.p), reinterpret_cast<float*>(pscale_.p));
+    std::vector<double> st((size_t)nb * dev::kBlockStats);
+    std::vector<float> ft((size_t)nb * dev::kMlpIn);
+    dev::d2h(st.data(), pstats_.p, st.size() * sizeof(double));
+    dev::d2h(ft.data(), pfeat_.p, ft.size() * sizeof(float));
+    for (int k = 0; k < nb; ++k) {
+        const double zx = st[(size_t)k * dev::kBlockStats + 3], zz = st[(size_t)k * dev::kBlockStats + 4];
+        if (!(zz > 0.0)) continue;
+        const double t = zx / zz;
+        if (!(t > 0.0)) continue;
+        hx_.insert(hx_.end(), ft.begin() + (size_t)k * dev::kMlpIn, ft.begin() + (size_t)(k + 1) * dev::kMlpIn);
+        ht_.push_back((float)std::min(20.0, std::max(0.05, t)));
+    }
+}
+
 void Engine::ensure_partials() {
     if (partials_.n >= (size_t)dev::kPartialsWords) return;
     partials_.ensure(dev::kPartialsWords);
@@ -1328,6 +1435,7 @@ int Engine::solve(int i, double& e2) {
     effop(1, i, LV_[i], RV_[i + 2], Ov, P0x_lay_[i], P0x_[i].p, lay, b_.p).run();
     build_diag(i, LH_[i], RH_[i + 2], O, lay, d_.p, -E0_);
     const EffOp& sig = effop(0, i, LH_[i], RH_[i + 2], O, lay, p_.p, lay, q_.p);
+    const int nb = (precond_ == 1 || harvest_) ? precond_blocks(lay) : 0;
     res_.t_phase[1] += dev::now() - t;
     t = dev::now();
     struct PhaseTimer {
@@ -1359,6 +1467,17 @@ int Engine::solve(int i, double& e2) {
     // and CG restarts from x when the updated residual has drifted.
     for (int restart = 0; restart < 4; ++restart) {
         dev::cg_init(r_.p, z_.p, p_.p, b_.p, q_.p, d_.p, n, scal_.p, partials_.p);
+        if (restart == 0 && precond_ == 1) {
+            // block scales from the initial residual, then the scaled start
+            precond_apply(i, nb);
+            dev::cg_init(r_.p, z_.p, p_.p, b_.p, q_.p, d_.p, n, scal_.p, partials_.p);
+        }
+        if (restart == 0 && harvest_) {  // initial residual and state, for the targets
+            pr0_.ensure(std::max<size_t>(n, 1));
+            px0_.ensure(std::max<size_t>(n, 1));
+            dev::d2d(pr0_.p, r_.p, n * sizeof(double));
+            dev::d2d(px0_.p, x_.p, n * sizeof(double));
+        }
         dev::d2h(sc, scal_.p, sizeof(sc));
         const double bb = sc[dev::S_BB];
         double rr = sc[dev::S_RR];
@@ -1418,6 +1537,7 @@ int Engine::solve(int i, double& e2) {
     dev::dot(x_.p, b_.p, n, scal_.p, dev::S_DOT, partials_.p);
     dev::d2h(sc, scal_.p, sizeof(sc));
     e2 = sc[dev::S_PQ] + 2.0 * sc[dev::S_DOT];
+    if (harvest_) harvest_window(i, nb);
     return it;
 }
 
@@ -1550,6 +1670,10 @@ SweepResult Engine::sweep(const SweepParams& p) {
     trace_.clear();
     cg_tol2_ = p.cg_rel_tol * p.cg_rel_tol;
     cg_max_ = p.cg_max_iter;
+    if (p.precond != 0 && p.precond != 1) throw err(MPSPT_E_ARG, "precond must be 0 (Jacobi) or 1 (learned)");
+    if (p.precond == 1 && !mlp_set_) throw err(MPSPT_E_STATE, "load the preconditioner network first");
+    if (p.precond == 1 && harvest_) throw err(MPSPT_E_ARG, "harvesting needs the Jacobi preconditioner");
+    precond_ = p.precond;
     clear_plans();  // plans are reused across the sweeps of one call only
     dev::sync();
     t0_ = dev::now();

@@ -223,6 +223,7 @@ struct StepRecord {
 
 struct SweepParams {
     int M1 = 16, n_sweeps = 0, max_sweeps = 10, cg_max_iter = 500, compute_e3 = 1;
+    int precond = 0;  // 0 Jacobi, 1 learned block scaling
     double e_tol = 1e-9, cg_rel_tol = 1e-10;
 };
 
@@ -263,6 +264,14 @@ class Engine {
     void site_dense(int which, int i, std::vector<double>& out, int& Dl, int& Dr) const;
 
     bool have_ints = false, have_part = false, have_psi0 = false, have_psi1 = false;
+
+    // learned preconditioner: parameters, training, harvested samples
+    void precond_set(const float* p, int n);
+    void precond_get(float* p, int n) const;
+    float mlp_step(const float* X, const float* t, int n, float lr, bool update, float* grad);
+    void set_harvest(bool on);
+    const std::vector<float>& harvest_X() const { return hx_; }
+    const std::vector<float>& harvest_t() const { return ht_; }
 
   private:
     // problem
@@ -317,6 +326,15 @@ class Engine {
     std::vector<std::unique_ptr<DiagPlan>> diag_plans_;
     void clear_plans();
     void ensure_partials();
+    // learned preconditioner state (floats stored in double buffers)
+    DevBuf mlp_, mlp_m_, mlp_v_, mlp_scr_, mlp_io_, pstats_, pfeat_, pscale_, pr0_, px0_;
+    DevArr<dev::BlockRef> pblocks_;
+    int mlp_step_ = 0, precond_ = 0;
+    bool mlp_set_ = false, harvest_ = false;
+    std::vector<float> hx_, ht_;
+    int precond_blocks(const Two& lay);  // uploads the block list, returns its length
+    void precond_apply(int i, int nb);
+    void harvest_window(int i, int nb);
     double* hsc_ = nullptr;  // pinned host copies of the CG scalars, two slots
     void* ev_[2] = {nullptr, nullptr};
     EffOp& effop(int r, int i, const Env& L, const Env& R, const TwoOp& O, const Two& ket, const double* xket,

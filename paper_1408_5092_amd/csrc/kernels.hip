@@ -25,16 +25,17 @@
 namespace mpspt {
 namespace dev {
 
-namespace {
-hipStream_t g_stream = nullptr;
-size_t g_lds_budget = 0;
-
+// shared with precond.hip
 void check(hipError_t e, const char* what) {
     if (e != hipSuccess) {
         int code = (e == hipErrorOutOfMemory) ? MPSPT_E_NOMEM : MPSPT_E_HIP;
         throw Error{code, std::string(what) + ": " + hipGetErrorString(e)};
     }
 }
+
+namespace {
+hipStream_t g_stream = nullptr;
+size_t g_lds_budget = 0;
 
 constexpr int RED_THREADS = 256;
 
@@ -790,8 +791,12 @@ int device_count() {
 }
 
 void set_device(int device, void* stream) {
-    int n = device_count();
-    if (device < 0 || device >= n) throw Error{MPSPT_E_NODEV, "no HIP device " + std::to_string(device)};
+    int n = 0;
+    const hipError_t e = hipGetDeviceCount(&n);
+    if (e != hipSuccess)
+        throw Error{MPSPT_E_NODEV, std::string("hipGetDeviceCount: ") + hipGetErrorString(e)};
+    if (device < 0 || device >= n)
+        throw Error{MPSPT_E_NODEV, "no HIP device " + std::to_string(device) + " (" + std::to_string(n) + " visible)"};
     check(hipSetDevice(device), "hipSetDevice");
     hipDeviceProp_t prop;
     check(hipGetDeviceProperties(&prop, device), "hipGetDeviceProperties");
@@ -884,6 +889,7 @@ void zero(void* p, size_t bytes) {
     check(hipMemsetAsync(p, 0, bytes, g_stream), "hipMemsetAsync");
 }
 void sync() { check(hipStreamSynchronize(g_stream), "hipStreamSynchronize"); }
+hipStream_t stream() { return g_stream; }
 void* host_alloc(size_t bytes) {
     void* p = nullptr;
     check(hipHostMalloc(&p, bytes, hipHostMallocDefault), "hipHostMalloc");

@@ -21,7 +21,9 @@ EXPORTED = ["mpspt_create", "mpspt_destroy", "mpspt_last_error", "mpspt_load_int
             "mpspt_load_integrals_eri", "mpspt_load_h0_partition", "mpspt_load_psi0",
             "mpspt_load_psi1_guess", "mpspt_ground_state", "mpspt_sweep", "mpspt_profile",
             "mpspt_kernel_stats", "mpspt_get_trace", "mpspt_get_bond",
-            "mpspt_get_site", "mpspt_mpo_dense", "mpspt_mpo_dims"]
+            "mpspt_get_site", "mpspt_mpo_dense", "mpspt_mpo_dims", "mpspt_precond_set", "mpspt_precond_get",
+            "mpspt_mlp_grad", "mpspt_mlp_train_step", "mpspt_harvest", "mpspt_harvest_get"]
+MLP_PARAMS, MLP_INPUTS = 4801, 8
 
 
 class MPSPTError(RuntimeError):
@@ -33,7 +35,7 @@ class MPSPTError(RuntimeError):
 class SweepParams(C.Structure):
     _fields_ = [("M1", C.c_int32), ("n_sweeps", C.c_int32), ("max_sweeps", C.c_int32),
                 ("e_tol", C.c_double), ("cg_rel_tol", C.c_double), ("cg_max_iter", C.c_int32),
-                ("compute_e3", C.c_int32)]
+                ("compute_e3", C.c_int32), ("precond", C.c_int32)]
 
 
 class Result(C.Structure):
@@ -55,6 +57,12 @@ def load_library(path: str | None = None):
     if path is None and _lib is not None:
         return _lib
     p = path or LIB_PATH
+    # PyTorch ships its own HIP runtime; loading it first makes the library
+    # bind to that same runtime instead of starting a second one
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     if not os.path.exists(p):
         raise ImportError(f"{p} is missing: build the HIP library first (python __graft_entry__.py build)")
     lib = C.CDLL(p)
@@ -79,6 +87,13 @@ def load_library(path: str | None = None):
     lib.mpspt_get_site.argtypes = [P, I, I, C.c_size_t, dp, ip]
     lib.mpspt_mpo_dense.argtypes = [I, I, dp, dp, dp, I, dp, C.c_size_t]
     lib.mpspt_mpo_dims.argtypes = [I, I, dp, dp, dp, I, ip, I]
+    fp = C.POINTER(C.c_float)
+    lib.mpspt_precond_set.argtypes = [P, fp, I]
+    lib.mpspt_precond_get.argtypes = [P, fp, I]
+    lib.mpspt_mlp_grad.argtypes = [P, fp, fp, I, fp, fp]
+    lib.mpspt_mlp_train_step.argtypes = [P, fp, fp, I, C.c_float, fp]
+    lib.mpspt_harvest.argtypes = [P, I]
+    lib.mpspt_harvest_get.argtypes = [P, C.c_int64, fp, fp, C.POINTER(C.c_int64)]
     for name in EXPORTED:
         if name not in ("mpspt_destroy", "mpspt_last_error"):
             getattr(lib, name).restype = C.c_int
@@ -179,14 +194,60 @@ class Context:
                                                 qn.ctypes.data_as(C.POINTER(C.c_int32)), ptrs))
 
     def sweep(self, M1, n_sweeps=0, max_sweeps=10, e_tol=1e-9, cg_rel_tol=1e-10, cg_max_iter=500,
-              compute_e3=True):
-        p = SweepParams(M1, n_sweeps, max_sweeps, e_tol, cg_rel_tol, cg_max_iter, int(bool(compute_e3)))
+              compute_e3=True, precond=0):
+        p = SweepParams(M1, n_sweeps, max_sweeps, e_tol, cg_rel_tol, cg_max_iter, int(bool(compute_e3)), int(precond))
         r = Result()
         self._ok(self.lib.mpspt_sweep(self.h, C.byref(p), C.byref(r)))
         out = {f: getattr(r, f) for f, _ in Result._fields_}
         out["e2_sweep"] = list(r.e2_sweep)[:r.n_sweeps_done]
         out["t_phase"] = dict(zip(("twoop", "build", "solve", "truncate", "env", "guess"), list(r.t_phase)))
         return out
+
+    # learned preconditioner
+    @staticmethod
+    def _f32(a, shape=None):
+        a = np.ascontiguousarray(a, dtype=np.float32)
+        if shape is not None and a.shape != shape:
+            raise ValueError(f"expected shape {shape}, got {a.shape}")
+        return a, a.ctypes.data_as(C.POINTER(C.c_float))
+
+    def precond_set(self, params):
+        a, pa = self._f32(params)
+        self._ok(self.lib.mpspt_precond_set(self.h, pa, a.size))
+
+    def precond_get(self):
+        out = np.zeros(MLP_PARAMS, dtype=np.float32)
+        self._ok(self.lib.mpspt_precond_get(self.h, out.ctypes.data_as(C.POINTER(C.c_float)), out.size))
+        return out
+
+    def mlp_grad(self, X, t):
+        Xa, px = self._f32(X)
+        ta, pt = self._f32(t)
+        g = np.zeros(MLP_PARAMS, dtype=np.float32)
+        loss = C.c_float()
+        self._ok(self.lib.mpspt_mlp_grad(self.h, px, pt, ta.size, g.ctypes.data_as(C.POINTER(C.c_float)),
+                                         C.byref(loss)))
+        return loss.value, g
+
+    def mlp_train_step(self, X, t, lr):
+        Xa, px = self._f32(X)
+        ta, pt = self._f32(t)
+        loss = C.c_float()
+        self._ok(self.lib.mpspt_mlp_train_step(self.h, px, pt, ta.size, lr, C.byref(loss)))
+        return loss.value
+
+    def harvest(self, enable=True):
+        self._ok(self.lib.mpspt_harvest(self.h, int(bool(enable))))
+
+    def harvest_get(self):
+        n = C.c_int64()
+        self._ok(self.lib.mpspt_harvest_get(self.h, 0, None, None, C.byref(n)))
+        X = np.zeros((n.value, MLP_INPUTS), dtype=np.float32)
+        t = np.zeros(n.value, dtype=np.float32)
+        if n.value:
+            self._ok(self.lib.mpspt_harvest_get(self.h, n.value, X.ctypes.data_as(C.POINTER(C.c_float)),
+                                                t.ctypes.data_as(C.POINTER(C.c_float)), C.byref(n)))
+        return X, t
 
     def profile(self, enable=True):
         self._ok(self.lib.mpspt_profile(self.h, int(bool(enable))))

@@ -63,9 +63,9 @@ def test_block_target_and_features():
     rng = np.random.default_rng(8)
     d = np.exp(rng.normal(0.0, 1.0, (3, 5)))
     b = rng.normal(0.0, 1.0, (3, 5))
-    x = 1.7 * (-b / d)
-    assert abs(mlp.block_target(d, b, x) - 1.7) < 1e-14
-    assert mlp.block_target(d, np.zeros((3, 5)), x) is None
+    e0 = 1.7 * (b / d)
+    assert abs(mlp.block_target(d, b, e0) - 1.7) < 1e-14
+    assert mlp.block_target(d, np.zeros((3, 5)), e0) is None
     f = mlp.block_features(np.full((2, 4), 3.0), b[:2, :4], 2.0 * np.linalg.norm(b[:2, :4]), 5, 12)
     np.testing.assert_allclose(f, [np.log(3.0), 0.0, 0.0, 0.0, np.log(2), np.log(4), -np.log(2.0), 0.5],
                                rtol=0, atol=1e-14)
