@@ -27,22 +27,31 @@ from .exact import keep_count
 SITE_DN = np.array([[0, 0], [1, 1], [1, -1], [2, 0]])
 
 
-def admissible(n, k_a, n_elec, two_sz, nv_allowed):
+def site_allowed(i, k_a, dn, virt_occ):
+    """May site i hold dn electrons?  virt_occ[j] is the set of electron
+    counts allowed on virtual site k_a + j (None: no restriction)."""
+    return virt_occ is None or i < k_a or dn in virt_occ[i - k_a]
+
+
+def admissible(n, k_a, n_elec, two_sz, nv_allowed, virt_occ=None):
     """Per bond: set of (N_left, 2Sz_left) through which a configuration with
-    n_elec electrons, total 2Sz and a virtual-electron count in nv_allowed can
-    pass (sites >= k_a are virtual)."""
+    n_elec electrons, total 2Sz, a virtual-electron count in nv_allowed and
+    (if given) per-virtual-site counts in virt_occ can pass (sites >= k_a are
+    virtual)."""
     left = [set() for _ in range(n + 1)]
     left[0].add((0, 0, 0))
     for i in range(n):
         for (a, s, v) in left[i]:
             for dn, ds in SITE_DN:
-                left[i + 1].add((a + dn, s + ds, v + (dn if i >= k_a else 0)))
+                if site_allowed(i, k_a, dn, virt_occ):
+                    left[i + 1].add((a + dn, s + ds, v + (dn if i >= k_a else 0)))
     right = [set() for _ in range(n + 1)]
     right[n].add((0, 0, 0))
     for i in range(n - 1, -1, -1):
         for (a, s, v) in right[i + 1]:
             for dn, ds in SITE_DN:
-                right[i].add((a + dn, s + ds, v + (dn if i >= k_a else 0)))
+                if site_allowed(i, k_a, dn, virt_occ):
+                    right[i].add((a + dn, s + ds, v + (dn if i >= k_a else 0)))
     out = []
     for b in range(n + 1):
         ok = set()
@@ -165,7 +174,7 @@ class Sweeper:
     """Two-site MPS-PT sweep, dense numpy (the oracle's O-B)."""
 
     def __init__(self, h, eri, k_a, eps_virt, n_elec, two_sz, psi0, psi1, M1,
-                 cg_tol=1e-10, cg_maxit=500):
+                 cg_tol=1e-10, cg_maxit=500, virt_occ=None):
         self.k_a = k_a
         self.n = n = h.shape[0]
         self.N, self.tsz, self.M = n_elec, two_sz, M1
@@ -174,7 +183,11 @@ class Sweeper:
         self.mpo_h0 = ops["H0"]()
         self.mpo_v = ops["V_psi0"]()
         self._mpo_vfull = ops["V"]
-        self.adm = admissible(n, k_a, n_elec, two_sz, (1, 2))
+        # virt_occ restricts Psi1 to the configurations with allowed electron
+        # counts on each virtual site (one virtual pair of the decomposition)
+        self.virt_occ = virt_occ
+        self.adm = admissible(n, k_a, n_elec, two_sz, (1, 2), virt_occ)
+        self.site_ok = np.array([[site_allowed(i, k_a, dn, virt_occ) for dn, _ in SITE_DN] for i in range(n)])
         # Psi0 on active sites, extended by empty virtual sites
         b0, s0 = psi0
         P0 = [np.array(a, dtype=float) for a in s0]
@@ -209,7 +222,8 @@ class Sweeper:
         qr = ql + SITE_DN[None, None, :, None, :]
         ok = np.all(qr == r[None, None, None, :, :], axis=-1)
         mid = np.array([[tuple(q) in self.adm[i + 1] for q in row] for row in ql[:, :, 0, 0, :]])
-        return ok & mid[:, :, None, None]
+        occ = self.site_ok[i][:, None] & self.site_ok[i + 1][None, :]
+        return ok & mid[:, :, None, None] & occ[None, :, :, None]
 
     # ---------------------------------------------------------- truncation
     def _select(self, groups, rho_of):

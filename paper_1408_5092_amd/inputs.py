@@ -66,14 +66,19 @@ def _site_counts(n_sites, virtual_from):
     return [i >= virtual_from for i in range(n_sites)]
 
 
-def bond_sectors(n_sites: int, k_a: int, n_elec: int, two_sz: int, nv_allowed):
+def _site_ok(i, k_a, dn, virt_occ):
+    return virt_occ is None or i < k_a or dn in virt_occ[i - k_a]
+
+
+def bond_sectors(n_sites: int, k_a: int, n_elec: int, two_sz: int, nv_allowed, virt_occ=None):
     """Sectors (N_left, 2Sz_left) that some admissible configuration passes
     through at every bond, with rough left/right configuration counts.
 
-    A configuration is admissible if it has n_elec electrons, total 2Sz, and a
+    A configuration is admissible if it has n_elec electrons, total 2Sz, a
     number of electrons in virtual orbitals (sites >= k_a) that lies in
-    nv_allowed.  Returns a list over bonds 0..n_sites of dicts
-    {(N, 2Sz): (count_left, count_right)}.
+    nv_allowed, and (if virt_occ is given) an electron count on the j-th
+    virtual site that lies in virt_occ[j].  Returns a list over bonds
+    0..n_sites of dicts {(N, 2Sz): (count_left, count_right)}.
     """
     virt = _site_counts(n_sites, k_a)
     # left DP over (N, 2Sz, nv) -> number of configurations
@@ -82,6 +87,8 @@ def bond_sectors(n_sites: int, k_a: int, n_elec: int, two_sz: int, nv_allowed):
     for i in range(n_sites):
         for (n, sz, nv), c in left[i].items():
             for dn, dsz in SITE_DN:
+                if not _site_ok(i, k_a, dn, virt_occ):
+                    continue
                 key = (n + dn, sz + dsz, nv + (dn if virt[i] else 0))
                 left[i + 1][key] = left[i + 1].get(key, 0) + c
     right = [dict() for _ in range(n_sites + 1)]
@@ -89,6 +96,8 @@ def bond_sectors(n_sites: int, k_a: int, n_elec: int, two_sz: int, nv_allowed):
     for i in range(n_sites - 1, -1, -1):
         for (n, sz, nv), c in right[i + 1].items():
             for dn, dsz in SITE_DN:
+                if not _site_ok(i, k_a, dn, virt_occ):
+                    continue
                 key = (n + dn, sz + dsz, nv + (dn if virt[i] else 0))
                 right[i][key] = right[i].get(key, 0) + c
     out = []
@@ -144,7 +153,7 @@ class MPSData:
 
 
 def random_mps(n_sites: int, k_a: int, n_elec: int, two_sz: int, nv_allowed,
-               M: int, seed: int) -> MPSData:
+               M: int, seed: int, virt_occ=None) -> MPSData:
     """Seeded random block-sparse MPS over the admissible sectors.
 
     Bond sector dimensions are min(left count, right count), then the largest
@@ -152,7 +161,7 @@ def random_mps(n_sites: int, k_a: int, n_elec: int, two_sz: int, nv_allowed,
     block entry is drawn from N(0, 1).
     """
     rng = np.random.default_rng(seed)
-    secs = bond_sectors(n_sites, k_a, n_elec, two_sz, set(nv_allowed))
+    secs = bond_sectors(n_sites, k_a, n_elec, two_sz, set(nv_allowed), virt_occ)
     bonds = [_dims(s, M) for s in secs]
     sites = []
     for i in range(n_sites):
