@@ -91,8 +91,27 @@ mpspt_status mpspt_load_psi0(mpspt_ctx *ctx, int32_t n_elec, int32_t two_sz, con
 mpspt_status mpspt_ground_state(mpspt_ctx *ctx, int32_t n_elec, int32_t two_sz, const int32_t *bond_dims,
                                 const int32_t *bond_qn, const double *const *site, int32_t M0,
                                 int32_t n_sweeps, double e_tol, double *e_out);
+/* Restrict Psi1 further: masks[k_v] gives, per virtual site, the electron
+ * counts it may hold (bit c set: c electrons allowed, so 7 allows all);
+ * masks = NULL restores 7 everywhere.  This is the pair decomposition of the
+ * paper's "Implementation" subsection (the embarrassing parallelisation over
+ * virtual pairs): Dyall's H0 keeps the virtual occupation pattern, so V|Psi0>
+ * splits into mutually orthogonal parts with independent first-order
+ * equations, and E2 is the sum of their Hylleraas minima.  With the
+ * integrals of the active orbitals plus virtual orbitals a < b, masks {2, 2}
+ * (one electron in each) select pair (a, b); with active plus a alone, mask
+ * {6} (one or two electrons) selects pair (a, a), which owns the singles.
+ * Lasts until the next mpspt_load_integrals*; invalidates a loaded Psi1 guess.
+ * Errors: MPSPT_E_STATE before integrals; MPSPT_E_ARG for a mask outside
+ * [1, 7], or, once Psi0 is loaded, for masks that some pair of admissible
+ * neighbouring bond labels would violate (the sweep restricts bond labels
+ * only; every label right of the active block fixes the electrons still to
+ * come, which suffices for the pair masks above). */
+mpspt_status mpspt_restrict_virtual(mpspt_ctx *ctx, const int32_t *masks);
+
 /* Starting first-order MPS on all k_a + k_v sites (same layout), restricted to
- * one or two electrons in virtual orbitals.  Required before mpspt_sweep. */
+ * one or two electrons in virtual orbitals and to the occupancy masks of
+ * mpspt_restrict_virtual.  Required before mpspt_sweep. */
 mpspt_status mpspt_load_psi1_guess(mpspt_ctx *ctx, const int32_t *bond_dims, const int32_t *bond_qn,
                                    const double *const *site);
 

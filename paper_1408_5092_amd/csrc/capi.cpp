@@ -8,6 +8,7 @@
 #include "engine.hpp"
 
 struct mpspt_ctx {
+    mpspt::dev::Stream* dev = nullptr;  // outlives eng: the engine's blocks go back to its pool
     mpspt::Engine eng;
     std::string err;
     int device = 0;
@@ -22,6 +23,7 @@ thread_local std::string g_err;
 template <class F>
 mpspt_status guard(mpspt_ctx* ctx, F&& f) {
     try {
+        if (ctx) mpspt::dev::bind(ctx->dev);
         f();
         return MPSPT_OK;
     } catch (const mpspt::dev::Error& e) {
@@ -108,8 +110,16 @@ mpspt_status mpspt_create(int hip_device, void* hip_stream, mpspt_ctx** out) {
     if (!out) return MPSPT_E_ARG;
     *out = nullptr;
     return guard(nullptr, [&] {
-        mpspt::dev::set_device(hip_device, hip_stream);
-        auto* c = new mpspt_ctx();
+        mpspt::dev::Stream* s = mpspt::dev::stream_create(hip_device, hip_stream);
+        mpspt::dev::bind(s);
+        mpspt_ctx* c = nullptr;
+        try {
+            c = new mpspt_ctx();
+        } catch (...) {
+            mpspt::dev::stream_destroy(s);
+            throw;
+        }
+        c->dev = s;
         c->device = hip_device;
         *out = c;
     });
@@ -118,8 +128,10 @@ mpspt_status mpspt_create(int hip_device, void* hip_stream, mpspt_ctx** out) {
 void mpspt_destroy(mpspt_ctx* ctx) {
     if (!ctx) return;
     try {
-        delete ctx;
-        mpspt::dev::trim();  // cached device blocks go back to the runtime
+        mpspt::dev::bind(ctx->dev);
+        mpspt::dev::Stream* s = ctx->dev;
+        delete ctx;                       // the engine's device blocks go back to the pool
+        mpspt::dev::stream_destroy(s);    // and the pool to the runtime
     } catch (...) {
     }
 }
@@ -184,6 +196,17 @@ mpspt_status mpspt_ground_state(mpspt_ctx* ctx, int32_t n_elec, int32_t two_sz, 
         double e = ctx->eng.ground_state(n_elec, two_sz, b, read_sites(b, site), M0, n_sweeps,
                                          e_tol > 0 ? e_tol : 1e-10);
         if (e_out) *e_out = e;
+    });
+}
+
+mpspt_status mpspt_restrict_virtual(mpspt_ctx* ctx, const int32_t* masks) {
+    if (!ctx) return MPSPT_E_ARG;
+    return guard(ctx, [&] {
+        if (!ctx->eng.have_ints) throw mpspt::dev::Error{MPSPT_E_STATE, "load integrals first"};
+        const int kv = ctx->eng.k_v();
+        std::vector<int> m(kv, 7);
+        if (masks) m.assign(masks, masks + kv);
+        ctx->eng.restrict_virtual(m);
     });
 }
 

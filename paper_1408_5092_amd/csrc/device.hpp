@@ -89,7 +89,14 @@ struct Error {
     std::string msg;
 };
 
-void set_device(int device, void* stream);  // throws Error
+// Device state of one library context: its device, its HIP stream, a caching
+// pool ordered on that stream and its profiling records.  Every call below
+// acts on the state bound to the calling thread, so contexts on different
+// threads (and streams) run side by side; one state serves one thread at a time.
+struct Stream;
+Stream* stream_create(int device, void* hip_stream);  // throws Error
+void stream_destroy(Stream* s);                        // waits for the stream, frees its pool
+void bind(Stream* s);                                  // make s current on this thread
 int device_count();
 void* alloc(size_t bytes);                  // throws Error (MPSPT_E_NOMEM); stream-ordered pool
 void release(void* p);                      // back to the pool; safe while earlier launches run

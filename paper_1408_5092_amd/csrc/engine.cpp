@@ -474,6 +474,7 @@ void Engine::set_integrals(int k_a, int k_v, std::vector<double> h, std::vector<
     n_ = k_a + k_v;
     h_ = std::move(h);
     eri_ = std::move(eri);
+    virt_occ_.assign(k_v, 7);
     have_ints = true;
     have_part = have_psi0 = have_psi1 = false;
 }
@@ -732,12 +733,41 @@ void Engine::set_psi0(int n_elec, int two_sz, const std::vector<Bond>& bonds,
         P0x_.back().alloc(std::max<size_t>(P0x_lay_.back().size, 1));
         contract_sites(P0_[i], P0_[i + 1], P0x_lay_.back(), P0x_.back().p);
     }
-    // admissible (N, 2Sz) at every bond of Psi1: one or two virtual electrons
+    compute_adm();
+    have_psi0 = true;
+    have_psi1 = false;
+}
+
+void Engine::restrict_virtual(const std::vector<int>& masks) {
+    if (!have_ints) throw err(MPSPT_E_STATE, "load integrals before restricting the virtual sites");
+    if ((int)masks.size() != k_v_) throw err(MPSPT_E_ARG, "one occupancy mask per virtual site");
+    for (int m : masks)
+        if (m < 1 || m > 7) throw err(MPSPT_E_ARG, "occupancy masks must lie in [1, 7]");
+    std::vector<int> prev = virt_occ_;
+    virt_occ_ = masks;
+    if (have_psi0) {
+        try {
+            compute_adm();
+        } catch (...) {
+            virt_occ_ = prev;
+            compute_adm();
+            throw;
+        }
+        clear_plans();
+        have_psi1 = false;
+    }
+}
+
+// Admissible (N, 2Sz) at every bond of Psi1: one or two virtual electrons, and
+// on each virtual site an electron count its mask allows.
+void Engine::compute_adm() {
+    auto site_ok = [&](int i, int s) { return i < k_a_ || ((virt_occ_[i - k_a_] >> site_dq(s).n) & 1); };
     std::vector<std::set<std::tuple<int, int, int>>> left(n_ + 1), right(n_ + 1);
     left[0].insert({0, 0, 0});
     for (int i = 0; i < n_; ++i)
         for (auto& t : left[i])
             for (int s = 0; s < 4; ++s) {
+                if (!site_ok(i, s)) continue;
                 QN d = site_dq(s);
                 left[i + 1].insert({std::get<0>(t) + d.n, std::get<1>(t) + d.s, std::get<2>(t) + (i >= k_a_ ? d.n : 0)});
             }
@@ -745,20 +775,29 @@ void Engine::set_psi0(int n_elec, int two_sz, const std::vector<Bond>& bonds,
     for (int i = n_ - 1; i >= 0; --i)
         for (auto& t : right[i + 1])
             for (int s = 0; s < 4; ++s) {
+                if (!site_ok(i, s)) continue;
                 QN d = site_dq(s);
                 right[i].insert({std::get<0>(t) + d.n, std::get<1>(t) + d.s, std::get<2>(t) + (i >= k_a_ ? d.n : 0)});
             }
-    adm_.assign(n_ + 1, {});
+    std::vector<std::set<QN>> adm(n_ + 1);
     for (int bb = 0; bb <= n_; ++bb)
         for (auto& l : left[bb])
             for (int nvr = 0; nvr <= 2; ++nvr) {
                 int nv = std::get<2>(l) + nvr;
                 if (nv < 1 || nv > 2) continue;
                 if (right[bb].count({N_ - std::get<0>(l), tsz_ - std::get<1>(l), nvr}))
-                    adm_[bb].insert(QN{std::get<0>(l), std::get<1>(l)});
+                    adm[bb].insert(QN{std::get<0>(l), std::get<1>(l)});
             }
-    have_psi0 = true;
-    have_psi1 = false;
+    // The sweep restricts only bond labels.  Every label to the right of the
+    // active block fixes the electron count still to come, so a site's count is
+    // the difference of its two labels; refuse masks that some pair of
+    // admissible neighbouring labels would violate.
+    for (int i = k_a_; i < n_; ++i)
+        for (const QN& l : adm[i])
+            for (int s = 0; s < 4; ++s)
+                if (adm[i + 1].count(l + site_dq(s)) && !site_ok(i, s))
+                    throw err(MPSPT_E_ARG, "virtual occupancy masks cannot be expressed through bond sectors");
+    adm_ = std::move(adm);
 }
 
 void Engine::set_psi1(const std::vector<Bond>& bonds, const std::vector<std::vector<double>>& sites) {

@@ -249,6 +249,8 @@ class Engine {
     void set_integrals(int k_a, int k_v, std::vector<double> h, std::vector<double> eri);
     void set_partition(std::vector<double> eps);
     void set_psi0(int n_elec, int two_sz, const std::vector<Bond>& bonds, const std::vector<std::vector<double>>& sites);
+    // Allowed electron counts per virtual site (bit c set: c electrons allowed); all 7 by default.
+    void restrict_virtual(const std::vector<int>& masks);
     void set_psi1(const std::vector<Bond>& bonds, const std::vector<std::vector<double>>& sites);
     SweepResult sweep(const SweepParams& p);
     // Two-site DMRG for the lowest state of H_act in (n_elec, two_sz) on the
@@ -285,6 +287,8 @@ class Engine {
     std::vector<DevBuf> P0x_;
     std::vector<Site> A_;       // Psi1
     std::vector<std::set<QN>> adm_;
+    std::vector<int> virt_occ_;  // per virtual site, bit c: c electrons allowed
+    void compute_adm();
     // environments
     std::vector<Env> LH_, RH_, LV_, RV_;
     // work buffers

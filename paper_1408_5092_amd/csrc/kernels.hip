@@ -16,6 +16,8 @@
 #include <cmath>
 #include <algorithm>
 #include <cstdio>
+#include <mutex>
+#include <string>
 #include <unordered_map>
 #include <vector>
 
@@ -34,8 +36,7 @@ void check(hipError_t e, const char* what) {
 }
 
 namespace {
-hipStream_t g_stream = nullptr;
-size_t g_lds_budget = 0;
+size_t g_lds_budget = 0;  // dynamic LDS granted to the eigensolver kernels (same on every gfx950)
 
 constexpr int RED_THREADS = 256;
 
@@ -790,7 +791,64 @@ int device_count() {
     return n;
 }
 
-void set_device(int device, void* stream) {
+struct ProfRec {
+    int kind;
+    hipEvent_t a, b;
+    double flops, bytes;
+};
+
+struct Stream {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    // caching pool
+    std::unordered_map<size_t, std::vector<void*>> free_blocks;
+    std::unordered_map<void*, size_t> block_size;
+    // profiling
+    bool prof = false;
+    std::vector<ProfRec> pending;
+    std::vector<hipEvent_t> event_pool;
+    KernelStats stats[K_COUNT];
+};
+
+namespace {
+thread_local Stream* t_cur = nullptr;
+thread_local int t_device = -1;
+std::mutex g_setup_mutex;
+std::vector<bool> g_setup_done;
+
+Stream& cur() {
+    if (!t_cur) throw Error{MPSPT_E_STATE, "no library context bound to this thread"};
+    return *t_cur;
+}
+hipStream_t cur_stream() { return cur().stream; }
+
+// Once per device: LDS left for the eigensolver next to at most ~25 KB of
+// static shared memory, granted to the kernels that take it dynamically.
+void setup_device(int device) {
+    std::lock_guard<std::mutex> lock(g_setup_mutex);
+    if ((int)g_setup_done.size() <= device) g_setup_done.resize(device + 1, false);
+    if (g_setup_done[device]) return;
+    hipDeviceProp_t prop;
+    check(hipGetDeviceProperties(&prop, device), "hipGetDeviceProperties");
+    if (std::string(prop.gcnArchName).rfind("gfx950", 0) != 0)
+        throw Error{MPSPT_E_NODEV, std::string("device is ") + prop.gcnArchName + ", the library is built for gfx950"};
+    int lds = 0;
+    check(hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, device), "hipDeviceGetAttribute");
+    const long budget = ((long)lds - 6 * EIG_MAXN * 8 - 1024) / 16 * 16;
+    if (budget < 4096) throw Error{MPSPT_E_NODEV, "not enough LDS for the eigensolver"};
+    if (g_lds_budget != 0 && g_lds_budget != (size_t)budget)
+        throw Error{MPSPT_E_NODEV, "devices with different LDS sizes"};
+    g_lds_budget = (size_t)budget;
+    const void* ks[] = {reinterpret_cast<const void*>(&k_eig_reduce<true>),
+                        reinterpret_cast<const void*>(&k_eig_vectors<true>),
+                        reinterpret_cast<const void*>(&k_eig_vectors<false>)};
+    for (const void* f : ks)
+        check(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)budget), "hipFuncSetAttribute");
+    g_setup_done[device] = true;
+}
+}  // namespace
+
+Stream* stream_create(int device, void* hip_stream) {
     int n = 0;
     const hipError_t e = hipGetDeviceCount(&n);
     if (e != hipSuccess)
@@ -798,23 +856,37 @@ void set_device(int device, void* stream) {
     if (device < 0 || device >= n)
         throw Error{MPSPT_E_NODEV, "no HIP device " + std::to_string(device) + " (" + std::to_string(n) + " visible)"};
     check(hipSetDevice(device), "hipSetDevice");
-    hipDeviceProp_t prop;
-    check(hipGetDeviceProperties(&prop, device), "hipGetDeviceProperties");
-    if (std::string(prop.gcnArchName).rfind("gfx950", 0) != 0)
-        throw Error{MPSPT_E_NODEV, std::string("device is ") + prop.gcnArchName + ", the library is built for gfx950"};
-    g_stream = static_cast<hipStream_t>(stream);
-    // dynamic LDS left for the eigensolver next to at most ~25 KB of static
-    // shared memory
-    int lds = 0;
-    check(hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, device), "hipDeviceGetAttribute");
-    const long budget = ((long)lds - 6 * EIG_MAXN * 8 - 1024) / 16 * 16;
-    if (budget < 4096) throw Error{MPSPT_E_NODEV, "not enough LDS for the eigensolver"};
-    g_lds_budget = (size_t)budget;
-    const void* ks[] = {reinterpret_cast<const void*>(&k_eig_reduce<true>),
-                        reinterpret_cast<const void*>(&k_eig_vectors<true>),
-                        reinterpret_cast<const void*>(&k_eig_vectors<false>)};
-    for (const void* f : ks)
-        check(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)budget), "hipFuncSetAttribute");
+    t_device = device;
+    setup_device(device);
+    Stream* s = new Stream();
+    s->device = device;
+    s->stream = static_cast<hipStream_t>(hip_stream);
+    return s;
+}
+
+void bind(Stream* s) {
+    t_cur = s;
+    if (s && t_device != s->device) {
+        check(hipSetDevice(s->device), "hipSetDevice");
+        t_device = s->device;
+    }
+}
+
+void stream_destroy(Stream* s) {
+    if (!s) return;
+    Stream* prev = t_cur;
+    bind(s);
+    (void)hipStreamSynchronize(s->stream);
+    for (auto& kv : s->free_blocks)
+        for (void* p : kv.second) (void)hipFree(p);
+    for (auto& r : s->pending) {
+        (void)hipEventDestroy(r.a);
+        (void)hipEventDestroy(r.b);
+    }
+    for (hipEvent_t ev : s->event_pool) (void)hipEventDestroy(ev);
+    // blocks still handed out (none once the engine is gone) stay with the runtime
+    delete s;
+    t_cur = prev == s ? nullptr : prev;
 }
 
 // Stream-ordered caching allocator.  All device work of the library is issued
@@ -823,9 +895,6 @@ void set_device(int device, void* stream) {
 // Sizes are rounded to 1/8 steps between powers of two; nothing is returned
 // to the runtime before trim().
 namespace {
-std::unordered_map<size_t, std::vector<void*>> g_free;
-std::unordered_map<void*, size_t> g_size;
-
 size_t size_class(size_t b) {
     if (b <= 256) return 256;
     size_t p = 1;
@@ -837,9 +906,10 @@ size_t size_class(size_t b) {
 
 void* alloc(size_t bytes) {
     if (bytes == 0) return nullptr;
+    Stream& st = cur();
     const size_t c = size_class(bytes);
-    auto it = g_free.find(c);
-    if (it != g_free.end() && !it->second.empty()) {
+    auto it = st.free_blocks.find(c);
+    if (it != st.free_blocks.end() && !it->second.empty()) {
         void* p = it->second.back();
         it->second.pop_back();
         return p;
@@ -852,44 +922,46 @@ void* alloc(size_t bytes) {
         e = hipMalloc(&p, c);
     }
     check(e, "hipMalloc");
-    g_size[p] = c;
+    st.block_size[p] = c;
     return p;
 }
 void release(void* p) {
     if (!p) return;
-    auto it = g_size.find(p);
-    if (it == g_size.end()) return;
-    g_free[it->second].push_back(p);
+    Stream& st = cur();
+    auto it = st.block_size.find(p);
+    if (it == st.block_size.end()) return;
+    st.free_blocks[it->second].push_back(p);
 }
 void trim() {
-    (void)hipStreamSynchronize(g_stream);
-    for (auto& kv : g_free)
+    Stream& st = cur();
+    (void)hipStreamSynchronize(st.stream);
+    for (auto& kv : st.free_blocks)
         for (void* p : kv.second) {
             (void)hipFree(p);
-            g_size.erase(p);
+            st.block_size.erase(p);
         }
-    g_free.clear();
+    st.free_blocks.clear();
 }
 void h2d(void* dst, const void* src, size_t bytes) {
     if (!bytes) return;
     // ordered on the stream; pageable sources are staged by the runtime before it returns
-    check(hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, g_stream), "hipMemcpyAsync H2D");
+    check(hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, cur_stream()), "hipMemcpyAsync H2D");
 }
 void d2h(void* dst, const void* src, size_t bytes) {
     if (!bytes) return;
-    check(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, g_stream), "hipMemcpyAsync D2H");
-    check(hipStreamSynchronize(g_stream), "hipStreamSynchronize");
+    check(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, cur_stream()), "hipMemcpyAsync D2H");
+    check(hipStreamSynchronize(cur_stream()), "hipStreamSynchronize");
 }
 void d2d(void* dst, const void* src, size_t bytes) {
     if (!bytes) return;
-    check(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, g_stream), "hipMemcpyAsync D2D");
+    check(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, cur_stream()), "hipMemcpyAsync D2D");
 }
 void zero(void* p, size_t bytes) {
     if (!bytes) return;
-    check(hipMemsetAsync(p, 0, bytes, g_stream), "hipMemsetAsync");
+    check(hipMemsetAsync(p, 0, bytes, cur_stream()), "hipMemsetAsync");
 }
-void sync() { check(hipStreamSynchronize(g_stream), "hipStreamSynchronize"); }
-hipStream_t stream() { return g_stream; }
+void sync() { check(hipStreamSynchronize(cur_stream()), "hipStreamSynchronize"); }
+hipStream_t stream() { return cur_stream(); }
 void* host_alloc(size_t bytes) {
     void* p = nullptr;
     check(hipHostMalloc(&p, bytes, hipHostMallocDefault), "hipHostMalloc");
@@ -900,7 +972,7 @@ void host_free(void* p) {
 }
 void d2h_async(void* dst, const void* src, size_t bytes) {
     if (!bytes) return;
-    check(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, g_stream), "hipMemcpyAsync D2H");
+    check(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, cur_stream()), "hipMemcpyAsync D2H");
 }
 void* event_create() {
     hipEvent_t e;
@@ -910,7 +982,7 @@ void* event_create() {
 void event_destroy(void* e) {
     if (e) (void)hipEventDestroy(static_cast<hipEvent_t>(e));
 }
-void event_record(void* e) { check(hipEventRecord(static_cast<hipEvent_t>(e), g_stream), "hipEventRecord"); }
+void event_record(void* e) { check(hipEventRecord(static_cast<hipEvent_t>(e), cur_stream()), "hipEventRecord"); }
 void event_wait(void* e) { check(hipEventSynchronize(static_cast<hipEvent_t>(e)), "hipEventSynchronize"); }
 double now() {
     using namespace std::chrono;
@@ -919,20 +991,12 @@ double now() {
 
 // ------------------------------------------------------------ profiling
 namespace {
-struct ProfRec {
-    int kind;
-    hipEvent_t a, b;
-    double flops, bytes;
-};
-bool g_prof = false;
-std::vector<ProfRec> g_pending;
-std::vector<hipEvent_t> g_event_pool;
-KernelStats g_stats[K_COUNT];
 
 hipEvent_t take_event() {
-    if (!g_event_pool.empty()) {
-        hipEvent_t e = g_event_pool.back();
-        g_event_pool.pop_back();
+    auto& pool = cur().event_pool;
+    if (!pool.empty()) {
+        hipEvent_t e = pool.back();
+        pool.pop_back();
         return e;
     }
     hipEvent_t e;
@@ -941,20 +1005,21 @@ hipEvent_t take_event() {
 }
 
 void prof_flush() {
-    if (g_pending.empty()) return;
-    check(hipEventSynchronize(g_pending.back().b), "hipEventSynchronize");
-    for (auto& r : g_pending) {
+    Stream& st = cur();
+    if (st.pending.empty()) return;
+    check(hipEventSynchronize(st.pending.back().b), "hipEventSynchronize");
+    for (auto& r : st.pending) {
         float ms = 0;
         check(hipEventElapsedTime(&ms, r.a, r.b), "hipEventElapsedTime");
-        KernelStats& s = g_stats[r.kind];
+        KernelStats& s = st.stats[r.kind];
         s.seconds += ms * 1e-3;
         s.flops += r.flops;
         s.bytes += r.bytes;
         s.launches++;
-        g_event_pool.push_back(r.a);
-        g_event_pool.push_back(r.b);
+        st.event_pool.push_back(r.a);
+        st.event_pool.push_back(r.b);
     }
-    g_pending.clear();
+    st.pending.clear();
 }
 
 // Launches on the library stream.  While recording, the launch goes through
@@ -962,13 +1027,14 @@ void prof_flush() {
 // start and end times, so the recorded durations are kernel execution only.
 template <typename F, typename... Args>
 void launch(int kind, double flops, double bytes, F kernel, dim3 grid, dim3 block, size_t shm, Args... args) {
-    if (g_prof) {
+    Stream& st = cur();
+    if (st.prof) {
         ProfRec r{kind, take_event(), take_event(), flops, bytes};
-        hipExtLaunchKernelGGL(kernel, grid, block, (uint32_t)shm, g_stream, r.a, r.b, 0, args...);
-        g_pending.push_back(r);
-        if (g_pending.size() >= 4096) prof_flush();
+        hipExtLaunchKernelGGL(kernel, grid, block, (uint32_t)shm, st.stream, r.a, r.b, 0, args...);
+        st.pending.push_back(r);
+        if (st.pending.size() >= 4096) prof_flush();
     } else {
-        hipLaunchKernelGGL(kernel, grid, block, shm, g_stream, args...);
+        hipLaunchKernelGGL(kernel, grid, block, shm, st.stream, args...);
     }
 }
 }  // namespace
@@ -978,17 +1044,18 @@ void launch(int kind, double flops, double bytes, F kernel, dim3 grid, dim3 bloc
 __global__ void k_profile_mark(int on) {}
 
 void profile_enable(bool on) {
-    if (g_prof) prof_flush();
-    g_prof = on;
-    for (auto& s : g_stats) s = KernelStats();
-    hipLaunchKernelGGL(k_profile_mark, dim3(1), dim3(64), 0, g_stream, on ? 1 : 0);
+    Stream& st = cur();
+    if (st.prof) prof_flush();
+    st.prof = on;
+    for (auto& s : st.stats) s = KernelStats();
+    hipLaunchKernelGGL(k_profile_mark, dim3(1), dim3(64), 0, cur_stream(), on ? 1 : 0);
     check(hipGetLastError(), "k_profile_mark");
 }
 
 KernelStats profile_stats(int kind) {
     prof_flush();
     if (kind < 0 || kind >= K_COUNT) return KernelStats();
-    return g_stats[kind];
+    return cur().stats[kind];
 }
 
 void gemm_grouped(const Bases& b, const GemmGroup* groups, int ngroups, const GemmTerm* terms, int ntiles,

@@ -19,7 +19,7 @@ STATUS = {0: "MPSPT_OK", -1: "MPSPT_E_ARG", -2: "MPSPT_E_QN", -3: "MPSPT_E_NOMEM
 
 EXPORTED = ["mpspt_create", "mpspt_destroy", "mpspt_last_error", "mpspt_load_integrals",
             "mpspt_load_integrals_eri", "mpspt_load_h0_partition", "mpspt_load_psi0",
-            "mpspt_load_psi1_guess", "mpspt_ground_state", "mpspt_sweep", "mpspt_profile",
+            "mpspt_restrict_virtual", "mpspt_load_psi1_guess", "mpspt_ground_state", "mpspt_sweep", "mpspt_profile",
             "mpspt_kernel_stats", "mpspt_get_trace", "mpspt_get_bond",
             "mpspt_get_site", "mpspt_mpo_dense", "mpspt_mpo_dims", "mpspt_precond_set", "mpspt_precond_get",
             "mpspt_mlp_grad", "mpspt_mlp_train_step", "mpspt_harvest", "mpspt_harvest_get"]
@@ -187,6 +187,15 @@ class Context:
                                              qn.ctypes.data_as(C.POINTER(C.c_int32)), ptrs, M0, n_sweeps, e_tol,
                                              C.byref(e)))
         return e.value
+
+    def restrict_virtual(self, masks=None):
+        """Per virtual site, a bit mask of the electron counts it may hold
+        (None: no restriction); see mpspt_restrict_virtual."""
+        if masks is None:
+            self._ok(self.lib.mpspt_restrict_virtual(self.h, None))
+            return
+        m = np.ascontiguousarray(masks, dtype=np.int32)
+        self._ok(self.lib.mpspt_restrict_virtual(self.h, m.ctypes.data_as(C.POINTER(C.c_int32))))
 
     def load_psi1_guess(self, bonds, sites):
         dims, qn, keep, ptrs = _mps_args(bonds, sites)

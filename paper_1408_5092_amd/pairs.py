@@ -1,0 +1,160 @@
+"""Virtual-pair decomposition of the first-order problem.
+
+Dyall's H0 keeps the occupation pattern of the virtual orbitals, and every
+term of V that survives on Psi0 puts one or two electrons into them, so
+V|Psi0> splits into parts that live on disjoint sets of patterns.  The
+first-order equation splits with it, and E2 is the sum of the Hylleraas
+minima of the parts: the parallelisation over virtual pairs that the paper
+mentions, without implementing it, in its "Implementation" subsection.
+
+Pair (a, b), a < b, owns the patterns with one electron in a and one in b;
+pair (a, a) owns those with one or two electrons in a, so the singles are
+carried by the diagonal pairs.  k_v virtual orbitals give k_v (k_v + 1) / 2
+pairs.  Each pair is a problem of its own on the active orbitals plus its
+one or two virtual orbitals: the integrals restricted to those orbitals, H0 =
+H_act + eps_a n_a (+ eps_b n_b), and Psi1 limited by per-site occupancy masks
+(``Context.restrict_virtual``).  E3 does not split this way (V couples
+different pairs), so only E2 is summed.
+
+Everything here is argument marshalling around the library's entry points;
+the sweeps themselves run in the HIP kernels behind them.
+"""
+from __future__ import annotations
+
+import queue
+import threading
+import time
+
+import numpy as np
+
+from . import mpspt
+
+ONE = 1 << 1             # mask bit: exactly one electron
+ONE_OR_TWO = (1 << 1) | (1 << 2)
+
+
+def pair_list(k_v: int):
+    """All pairs (a, b) with 0 <= a <= b < k_v, a-major."""
+    return [(a, b) for a in range(k_v) for b in range(a, k_v)]
+
+
+def pair_masks(a: int, b: int):
+    """Occupancy masks of the pair's virtual sites (in the order a, b)."""
+    return [ONE, ONE] if a < b else [ONE_OR_TWO]
+
+
+def mask_sets(masks):
+    """Masks as sets of allowed electron counts (the form the MPS generators take)."""
+    return [{c for c in range(3) if (m >> c) & 1} for m in masks]
+
+
+def pair_orbitals(k_a: int, a: int, b: int):
+    """Orbitals of pair (a, b): all active ones, then virtual a (and b)."""
+    return list(range(k_a)) + [k_a + a] + ([k_a + b] if b != a else [])
+
+
+def pair_integrals(h, B, k_a: int, eps_virt, a: int, b: int):
+    """(h, Cholesky vectors, virtual energies) restricted to the pair's orbitals."""
+    orbs = pair_orbitals(k_a, a, b)
+    h = np.asarray(h, dtype=np.float64)
+    B = np.asarray(B, dtype=np.float64)
+    hp = np.ascontiguousarray(h[np.ix_(orbs, orbs)])
+    Bp = np.ascontiguousarray(B[:, orbs][:, :, orbs])
+    ep = np.ascontiguousarray(np.asarray(eps_virt, dtype=np.float64)[[a] + ([b] if b != a else [])])
+    return hp, Bp, ep
+
+
+def solve_pair(ctx: "mpspt.Context", h, B, k_a: int, eps_virt, n_elec: int, two_sz: int, psi0, a: int, b: int,
+               guess, M1: int, **sweep_kw):
+    """One pair's sweep on ``ctx``.
+
+    psi0: (bonds, sites) of the active-space reference; guess: (bonds,
+    sites) of the pair's starting Psi1 on k_a + 1 (a == b) or k_a + 2 sites,
+    within the pair's occupancy masks.  Returns the sweep's result dict.
+    """
+    hp, Bp, ep = pair_integrals(h, B, k_a, eps_virt, a, b)
+    ctx.load_integrals(k_a, len(ep), hp, Bp)
+    ctx.load_h0_partition(ep)
+    ctx.load_psi0(n_elec, two_sz, *psi0)
+    ctx.restrict_virtual(pair_masks(a, b))
+    ctx.load_psi1_guess(*guess)
+    sweep_kw.setdefault("compute_e3", False)
+    return ctx.sweep(M1, **sweep_kw)
+
+
+def solve_pairs(ctx: "mpspt.Context", h, B, k_a: int, eps_virt, n_elec: int, two_sz: int, psi0, guess_of,
+                M1: int, pairs=None, **sweep_kw):
+    """Sweeps over ``pairs`` (default: all of them), one after another on ``ctx``.
+
+    guess_of(a, b) returns the pair's starting Psi1.  Returns
+    (E2 summed over the pairs, {pair: result dict}, wall seconds).
+    """
+    k_v = len(eps_virt)
+    pairs = pair_list(k_v) if pairs is None else list(pairs)
+    out = {}
+    t0 = time.perf_counter()
+    for (a, b) in pairs:
+        out[(a, b)] = solve_pair(ctx, h, B, k_a, eps_virt, n_elec, two_sz, psi0, a, b, guess_of(a, b), M1,
+                                 **sweep_kw)
+    dt = time.perf_counter() - t0
+    return sum(r["e2"] for r in out.values()), out, dt
+
+
+def make_contexts(n: int, device: int = 0):
+    """n library contexts on ``device``, each on a stream of its own (default
+    priority), for ``solve_pairs_concurrent``."""
+    import ctypes
+
+    import torch
+    out = []
+    for _ in range(n):
+        st = torch.cuda.Stream(device=device)
+        ctx = mpspt.Context(device, stream=ctypes.c_void_p(st.cuda_stream))
+        ctx._stream = st  # the stream must outlive the context
+        out.append(ctx)
+    return out
+
+
+def solve_pairs_concurrent(contexts, h, B, k_a: int, eps_virt, n_elec: int, two_sz: int, psi0, guess_of,
+                           M1: int, pairs=None, **sweep_kw):
+    """Like ``solve_pairs``, with the pairs spread over one host thread per
+    context.  Each context has its own stream, so one pair's host work (work
+    lists, truncation bookkeeping, waits for convergence flags) overlaps the
+    kernels of the others.  Pairs with two virtual sites are handed out
+    first (they take longer).  Results do not depend on the number of
+    contexts: every pair's sweep is the same sequence of launches on its
+    context's stream."""
+    k_v = len(eps_virt)
+    pairs = pair_list(k_v) if pairs is None else list(pairs)
+    work = queue.Queue()
+    for p in sorted(pairs, key=lambda p: p[0] == p[1]):
+        work.put(p)
+    out, errors = {}, []
+    lock = threading.Lock()
+
+    def worker(ctx):
+        while not errors:
+            try:
+                a, b = work.get_nowait()
+            except queue.Empty:
+                return
+            try:
+                r = solve_pair(ctx, h, B, k_a, eps_virt, n_elec, two_sz, psi0, a, b, guess_of(a, b), M1,
+                               **sweep_kw)
+            except BaseException as e:  # noqa: BLE001 - re-raised below
+                with lock:
+                    errors.append(e)
+                return
+            with lock:
+                out[(a, b)] = r
+
+    t0 = time.perf_counter()
+    threads = [threading.Thread(target=worker, args=(c,)) for c in contexts]
+    for t in threads:
+        t.start()
+    for t in threads:
+        t.join()
+    dt = time.perf_counter() - t0
+    if errors:
+        raise errors[0]
+    return sum(out[p]["e2"] for p in sorted(out)), out, dt
