@@ -174,7 +174,7 @@ def main():
         print(f"[bench] step {k}: {walls[-1]:.3f}s E2={res['e2']:.12f} E3={res['e3']:.12f} "
               f"t(1uEh)={t2u[-1]} host phases " +
               " ".join(f"{kk}={v:.3f}" for kk, v in res["t_phase"].items()), file=sys.stderr, flush=True)
-    stats = {kk: ctx.kernel_stats(kk) for kk in range(6)}
+    stats = {kk: ctx.kernel_stats(kk) for kk in sorted(ctx.KERNELS)}
     ctx.profile(False)
 
     dom = max(stats.values(), key=lambda s: s["seconds"])

@@ -124,6 +124,15 @@ typedef struct {
     int32_t cg_max_iter;  /* cap on CG iterations per local solve */
     int32_t compute_e3;   /* 1: evaluate E3 on the final state */
     int32_t precond;      /* 0: Jacobi; 1: learned block scaling (mpspt_precond_set first) */
+    int32_t precision;    /* sigma inside CG: 0 FP64; 1 FP32 (MFMA); 2 BF16x3 (three BF16 MFMA
+                             products of split FP32 operands, FP32 accumulation).  With 1 or 2
+                             each CG round stops once it has cut its starting residual by
+                             inner_rel_tol, and the solve restarts from the FP64 residual
+                             -b - A x (iterative refinement) until that meets cg_rel_tol, so the
+                             converged tensors meet the same FP64 test as precision 0.  Right-hand
+                             side, diagonal, environments, Hylleraas value, truncation and E3
+                             stay FP64. */
+    double inner_rel_tol; /* 0: default (1e-5 for FP32, 1e-3 for BF16x3) */
 } mpspt_sweep_params;
 
 typedef struct {
@@ -145,6 +154,8 @@ typedef struct {
     int64_t plan_builds;    /* work lists built for this call (environment updates, sigma, right-hand
                              * side, diagonal) */
     int64_t plan_hits;      /* work lists replayed because the block layouts were unchanged */
+    int64_t sigma_lo_calls; /* of sigma_calls, those in reduced precision */
+    int64_t refinements;    /* CG restarts from an FP64 residual after a converged inner round */
 } mpspt_result;
 
 /* Run the sweep.  Errors: MPSPT_E_STATE if integrals, partition, Psi0 or the
@@ -190,7 +201,8 @@ mpspt_status mpspt_harvest_get(mpspt_ctx *ctx, int64_t cap, float *X, float *t, 
  * returns, for kind 0 = grouped GEMM (k_gemm_grouped), 1 = grouped block
  * axpy, 2 = tridiagonal reduction and eigenvalues (k_eig_reduce), 3 = Jacobi
  * diagonal, 4 = kept-subspace bases (k_eig_vectors), 5 = CG / Davidson
- * vector kernels, the summed event time,
+ * vector kernels, 6 = reduced-precision grouped GEMM (k_gemm_grouped_lo),
+ * 7 = reduced-precision block axpy, the summed event time,
  * launch count and the algorithmic flops / bytes of those launches (flops
  * 2mnk per block product; bytes: every operand block read once and every
  * output block written once).  Waits for outstanding launches. */

@@ -233,6 +233,8 @@ mpspt_status mpspt_sweep(mpspt_ctx* ctx, const mpspt_sweep_params* params, mpspt
         p.cg_max_iter = params->cg_max_iter > 0 ? params->cg_max_iter : 500;
         p.compute_e3 = params->compute_e3;
         p.precond = params->precond;
+        p.precision = params->precision;
+        p.inner_rel_tol = params->inner_rel_tol;
         if (p.n_sweeps > 64 || p.n_sweeps < 0) throw argerr("n_sweeps must be in [0, 64]");
         mpspt::SweepResult r = ctx->eng.sweep(p);
         std::memset(out, 0, sizeof(*out));
@@ -252,6 +254,8 @@ mpspt_status mpspt_sweep(mpspt_ctx* ctx, const mpspt_sweep_params* params, mpspt
         for (int k = 0; k < 6; ++k) out->t_phase[k] = r.t_phase[k];
         out->plan_builds = r.plan_builds;
         out->plan_hits = r.plan_hits;
+        out->sigma_lo_calls = r.sigma_lo_calls;
+        out->refinements = r.refinements;
     });
 }
 

@@ -22,6 +22,10 @@ constexpr int kAbsSlot = kSlots - 1;
 struct Bases {
     double* p[kSlots];
 };
+// The same slots over FP32 copies (reduced-precision sigma; no absolute slot).
+struct BasesF {
+    float* p[kSlots];
+};
 
 // C (m x n, leading dimension ldc) [+]= sum_t alpha_t op(A_t) op(B_t), computed in
 // GEMM_TILE x GEMM_TILE output tiles
@@ -124,7 +128,8 @@ void axpy_grouped(const Bases& b, const AxpyGroup* groups, int ngroups, const Ax
                   double bytes = 0);
 
 // Per-kernel timing with HIP events recorded on the library's stream.
-enum KernelKind { K_GEMM = 0, K_AXPY = 1, K_EIG = 2, K_DIAG = 3, K_EIGV = 4, K_VEC = 5, K_COUNT = 6 };
+enum KernelKind { K_GEMM = 0, K_AXPY = 1, K_EIG = 2, K_DIAG = 3, K_EIGV = 4, K_VEC = 5, K_GEMM_LO = 6, K_AXPY_LO = 7,
+                  K_COUNT = 8 };
 struct KernelStats {
     double seconds = 0, flops = 0, bytes = 0;
     long long launches = 0;
@@ -161,6 +166,18 @@ void cg_update(double* x, double* r, double* z, const double* p, const double* q
 void cg_direction(double* p, const double* z, size_t n, const double* scal, int rz_cur, int rz_new);
 // y = a x + b y
 void axpby(double* y, const double* x, double a, double b, size_t n);
+// Reduced-precision sigma (mode 1: FP32 MFMA, 2: BF16x3 split products with
+// FP32 accumulation) over the same work lists, on FP32 operand copies.
+void gemm_grouped_lo(const BasesF& b, int mode, const GemmGroup* groups, int ngroups, const GemmTerm* terms,
+                     int ntiles, double flops = 0, double bytes = 0);
+void axpy_grouped_lo(const BasesF& b, const AxpyGroup* groups, int ngroups, const AxpyTerm* terms, double flops = 0,
+                     double bytes = 0);
+void to_f32(float* dst, const double* src, size_t n);
+// p = z + beta p as in cg_direction, also written to pf in FP32
+void cg_direction_lo(double* p, float* pf, const double* z, size_t n, const double* scal, int rz_cur, int rz_new);
+// q = qf - shift * p (qf: FP32 product) ; scal[PQ] = p.q
+void cg_shift_dot_lo(double* q, const float* qf, const double* p, double shift, size_t n, double* scal,
+                     double* partials);
 // t = r / (theta - d), with |theta - d| floored at 1e-8 (Davidson correction)
 void davidson_precond(double* t, const double* r, const double* d, double theta, size_t n);
 

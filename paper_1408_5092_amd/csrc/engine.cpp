@@ -283,6 +283,7 @@ void GemmBatch::group(double* C, int ldc, int m, int n, bool acc) {
         return;
     }
     slots_.ref(C, g.sc, g.oc);
+    if (g.sc == dev::kAbsSlot) abs_ = true;
     g.ldc = ldc;
     g.m = m;
     g.n = n;
@@ -298,6 +299,7 @@ void GemmBatch::term(const double* A, int lda, bool tA, const double* B, int ldb
     dev::GemmTerm t{};
     slots_.ref(A, t.sa, t.oa);
     slots_.ref(B, t.sb, t.ob);
+    if (t.sa == dev::kAbsSlot || t.sb == dev::kAbsSlot) abs_ = true;
     t.alpha = alpha;
     t.lda = lda;
     t.ldb = ldb;
@@ -417,6 +419,13 @@ void GemmBatch::run() const {
     if (tiles_ > 0) dev::gemm_grouped(b, dg_.p, (int)g_.size(), dt_.p, tiles_, flops_, bytes_);
     red_.run(b);
 }
+void GemmBatch::run_lo(const dev::BasesF& b, int mode) const {
+    if (abs_) throw err(MPSPT_E_STATE, "reduced-precision work list refers outside its bound buffers");
+    dev::BasesF c = b;
+    c.p[kPartSlot] = reinterpret_cast<float*>(part_.p);
+    if (tiles_ > 0) dev::gemm_grouped_lo(c, mode, dg_.p, (int)g_.size(), dt_.p, tiles_, flops_, bytes_ / 2);
+    red_.run_lo(c);
+}
 
 void AxpyBatch::group(double* dst, int ldd, int m, int n, bool acc) {
     int8_t sl;
@@ -425,6 +434,7 @@ void AxpyBatch::group(double* dst, int ldd, int m, int n, bool acc) {
     group_ref(sl, off, ldd, m, n, acc);
 }
 void AxpyBatch::group_ref(int8_t slot, int64_t off, int ldd, int m, int n, bool acc) {
+    if (slot == dev::kAbsSlot) abs_ = true;
     dev::AxpyGroup g{};
     g.sd = slot;
     g.od = off;
@@ -443,6 +453,7 @@ void AxpyBatch::term(const double* src, int lds, bool trans, double alpha) {
     term_ref(sl, off, lds, trans, alpha);
 }
 void AxpyBatch::term_ref(int8_t slot, int64_t off, int lds, bool trans, double alpha) {
+    if (slot == dev::kAbsSlot) abs_ = true;
     dev::AxpyGroup& g = g_.back();
     dev::AxpyTerm t{};
     t.ss = slot;
@@ -465,6 +476,10 @@ void AxpyBatch::upload() {
 }
 void AxpyBatch::run(const dev::Bases& b) const {
     if (!g_.empty()) dev::axpy_grouped(b, dg_.p, (int)g_.size(), dt_.p, flops_, bytes_);
+}
+void AxpyBatch::run_lo(const dev::BasesF& b) const {
+    if (abs_) throw err(MPSPT_E_STATE, "reduced-precision work list refers outside its bound buffers");
+    if (!g_.empty()) dev::axpy_grouped_lo(b, dg_.p, (int)g_.size(), dt_.p, flops_, bytes_ / 2);
 }
 
 // ------------------------------------------------------------- inputs
@@ -1489,6 +1504,36 @@ int Engine::solve(int i, double& e2) {
         res_.flops += sig.flops;
         res_.bytes += sig.bytes;
     };
+    // Reduced precision: the CG iterations apply the operator on FP32 copies
+    // of the environments and the direction; every restart recomputes the
+    // residual -b - A x in FP64 (iterative refinement), so the converged x
+    // meets the same FP64 residual test as the plain solve.
+    const bool lo = precision_ != 0;
+    dev::BasesF fb{};
+    if (lo) {
+        const Env& L = LH_[i];
+        const Env& R = RH_[i + 2];
+        auto words = [](size_t floats) { return std::max<size_t>((floats + 1) / 2, 1); };
+        lf_.ensure(words(L.size));
+        rf_.ensure(words(R.size));
+        pf_.ensure(words(n));
+        qf_.ensure(words(n));
+        fb.p[0] = reinterpret_cast<float*>(lf_.p);
+        fb.p[1] = reinterpret_cast<float*>(rf_.p);
+        fb.p[2] = reinterpret_cast<float*>(pf_.p);
+        fb.p[3] = reinterpret_cast<float*>(qf_.p);
+        dev::to_f32(fb.p[0], L.data.p, L.size);
+        dev::to_f32(fb.p[1], R.data.p, R.size);
+    }
+    auto apply_inner = [&]() {
+        if (!lo) return apply();
+        sig.run_lo(fb, precision_);
+        dev::cg_shift_dot_lo(q_.p, fb.p[3], p_.p, E0_, n, scal_.p, partials_.p);
+        res_.sigma_calls++;
+        res_.sigma_lo_calls++;
+        res_.flops += sig.flops;
+        res_.bytes += sig.bytes / 2;
+    };
     double sc[dev::S_N];
     // start from the best multiple of the guess: x0 <- a x0, a = -x0.b / x0.A x0
     dev::d2d(x_.p, xg_.p, n * sizeof(double));
@@ -1502,9 +1547,11 @@ int Engine::solve(int i, double& e2) {
         dev::axpby(q_.p, q_.p, 0.0, a, n);
     }
     int it = 0;
+    bool solved = false;
     // CG on A x = -b; convergence is confirmed on the true residual -b - A x
     // and CG restarts from x when the updated residual has drifted.
-    for (int restart = 0; restart < 4; ++restart) {
+    const int max_restarts = lo ? 12 : 4;
+    for (int restart = 0;; ++restart) {
         dev::cg_init(r_.p, z_.p, p_.p, b_.p, q_.p, d_.p, n, scal_.p, partials_.p);
         if (restart == 0 && precond_ == 1) {
             // block scales from the initial residual, then the scaled start
@@ -1523,13 +1570,19 @@ int Engine::solve(int i, double& e2) {
         if (bb == 0.0) {
             dev::zero(x_.p, n * sizeof(double));
             dev::zero(q_.p, n * sizeof(double));
+            solved = true;
             break;
         }
-        if (rr <= cg_tol2_ * bb) break;
-        if (it >= cg_max_) {
-            res_.flags |= 1;
+        if (rr <= cg_tol2_ * bb) {
+            solved = true;
             break;
         }
+        if (it >= cg_max_ || restart == max_restarts) break;  // not converged: flagged below
+        if (restart > 0) res_.refinements++;
+        // an inner (reduced-precision) round stops once it has cut its own
+        // starting residual by inner_rel_tol, or at the final tolerance
+        const double stop2 = std::max(cg_tol2_ * bb, inner_tol2_ * rr);
+        if (lo) dev::to_f32(fb.p[2], p_.p, n);
         // Iteration k's scalars go to pinned slot k % 2; the host examines
         // iteration k - 1 while iteration k runs, so the device never waits
         // for the host.  When k - 1 has converged, x carries the one extra
@@ -1543,11 +1596,12 @@ int Engine::solve(int i, double& e2) {
         bool conv = false;
         while (!conv) {
             if (it < cg_max_) {
-                apply();
+                apply_inner();
                 dev::cg_update(x_.p, r_.p, z_.p, p_.p, q_.p, d_.p, n, scal_.p, cur, nxt, partials_.p);
                 dev::d2h_async(hsc_ + (it & 1) * dev::S_N, scal_.p, dev::S_N * sizeof(double));
                 dev::event_record(ev_[it & 1]);
-                dev::cg_direction(p_.p, z_.p, n, scal_.p, cur, nxt);
+                if (lo) dev::cg_direction_lo(p_.p, fb.p[2], z_.p, n, scal_.p, cur, nxt);
+                else dev::cg_direction(p_.p, z_.p, n, scal_.p, cur, nxt);
                 std::swap(cur, nxt);
                 ++it;
             } else if (seen == it) {
@@ -1561,7 +1615,7 @@ int Engine::solve(int i, double& e2) {
                 if (!(h[dev::S_PQ] > 0.0))
                     throw err(MPSPT_E_INDEFINITE, "CG met p.Ap <= 0: H0 - E0 is not positive definite on the local space");
                 rr = h[dev::S_RR];
-                if (rr <= cg_tol2_ * bb) {
+                if (rr <= stop2) {
                     conv = true;
                     break;
                 }
@@ -1570,6 +1624,7 @@ int Engine::solve(int i, double& e2) {
         dev::d2d(p_.p, x_.p, n * sizeof(double));
         apply();  // q = A x, scal[PQ] = x.A x
     }
+    if (!solved) res_.flags |= 1;  // iteration cap, or restarts exhausted above the tolerance
     // Hylleraas value of x: x.(A x) + 2 x.b  (q = A x from the last application)
     dev::d2d(p_.p, x_.p, n * sizeof(double));
     dev::cg_shift_dot(q_.p, p_.p, 0.0, n, scal_.p, partials_.p);
@@ -1713,6 +1768,14 @@ SweepResult Engine::sweep(const SweepParams& p) {
     if (p.precond == 1 && !mlp_set_) throw err(MPSPT_E_STATE, "load the preconditioner network first");
     if (p.precond == 1 && harvest_) throw err(MPSPT_E_ARG, "harvesting needs the Jacobi preconditioner");
     precond_ = p.precond;
+    if (p.precision < 0 || p.precision > 2) throw err(MPSPT_E_ARG, "precision must be 0 (FP64), 1 (FP32) or 2 (BF16x3)");
+    if (!(p.inner_rel_tol >= 0.0 && p.inner_rel_tol < 1.0)) throw err(MPSPT_E_ARG, "inner_rel_tol must lie in [0, 1)");
+    precision_ = p.precision;
+    {
+        // default inner reduction: a little above what the product's rounding allows
+        const double inner = p.inner_rel_tol > 0 ? p.inner_rel_tol : (precision_ == 1 ? 1e-5 : 1e-3);
+        inner_tol2_ = precision_ ? inner * inner : 0.0;
+    }
     clear_plans();  // plans are reused across the sweeps of one call only
     dev::sync();
     t0_ = dev::now();

@@ -139,7 +139,7 @@ class SlotMap {
 // Work list of grouped block axpys, reusable across launches.
 class AxpyBatch {
   public:
-    void clear() { g_.clear(); t_.clear(); flops_ = 0; bytes_ = 0; }
+    void clear() { g_.clear(); t_.clear(); flops_ = 0; bytes_ = 0; abs_ = false; }
     void bind(int slot, const double* base, size_t count) { slots_.bind(slot, base, count); }
     void group(double* dst, int ldd, int m, int n, bool acc);
     void term(const double* src, int lds, bool trans, double alpha);
@@ -149,6 +149,7 @@ class AxpyBatch {
     void upload();
     void run() const { run(slots_.bases()); }
     void run(const dev::Bases& b) const;
+    void run_lo(const dev::BasesF& b) const;  // FP32 copies of the slots
     bool empty() const { return g_.empty(); }
     double flops() const { return flops_; }
     double bytes() const { return bytes_; }
@@ -160,6 +161,7 @@ class AxpyBatch {
     DevArr<dev::AxpyGroup> dg_;
     DevArr<dev::AxpyTerm> dt_;
     double flops_ = 0, bytes_ = 0;
+    bool abs_ = false;  // some reference lies outside the bound slots
 };
 
 // Work list of grouped GEMMs, reusable across launches.  Slot kPartSlot is
@@ -167,12 +169,15 @@ class AxpyBatch {
 class GemmBatch {
   public:
     static constexpr int kPartSlot = dev::kAbsSlot - 1;
-    void clear() { g_.clear(); t_.clear(); tiles_ = 0; flops_ = 0; bytes_ = 0; red_.clear(); split_ = false; }
+    void clear() { g_.clear(); t_.clear(); tiles_ = 0; flops_ = 0; bytes_ = 0; red_.clear(); split_ = false; abs_ = false; }
     void bind(int slot, const double* base, size_t count) { slots_.bind(slot, base, count); }
     void group(double* C, int ldc, int m, int n, bool acc);
     void term(const double* A, int lda, bool tA, const double* B, int ldb, bool tB, int k, double alpha);
     void upload();
     void run() const;
+    // mode 1: FP32, 2: BF16x3, on FP32 copies of the slots (the split-k
+    // scratch is reused as FP32)
+    void run_lo(const dev::BasesF& b, int mode) const;
     bool empty() const { return g_.empty(); }
     double flops() const { return flops_; }
     double bytes() const { return bytes_; }  // operand blocks read once, output blocks written once
@@ -189,6 +194,7 @@ class GemmBatch {
     AxpyBatch red_;  // sums split-k partials into the outputs
     DevBuf part_;
     bool split_ = false;
+    bool abs_ = false;
 };
 
 // y = sum L (x) O (x) R applied to x (three grouped launches).  Slots:
@@ -205,6 +211,14 @@ struct EffOp {
         st3.bind(slot, base, count);
     }
     void run() const { st1.run(); st2.run(); st3.run(); }
+    // Reduced precision: slots 0..3 as FP32 copies, U and V reused as FP32.
+    void run_lo(dev::BasesF b, int mode) const {
+        b.p[4] = reinterpret_cast<float*>(U.p);
+        b.p[5] = reinterpret_cast<float*>(V.p);
+        st1.run_lo(b, mode);
+        st2.run_lo(b);
+        st3.run_lo(b, mode);
+    }
 };
 
 // Layout signature of the inputs a work list was built from; a cached list
@@ -224,7 +238,10 @@ struct StepRecord {
 struct SweepParams {
     int M1 = 16, n_sweeps = 0, max_sweeps = 10, cg_max_iter = 500, compute_e3 = 1;
     int precond = 0;  // 0 Jacobi, 1 learned block scaling
-    double e_tol = 1e-9, cg_rel_tol = 1e-10;
+    // sigma inside CG: 0 FP64, 1 FP32, 2 BF16x3; with 1 or 2 the solve is
+    // refined on FP64 residuals, each inner CG cutting its residual by inner_rel_tol
+    int precision = 0;
+    double e_tol = 1e-9, cg_rel_tol = 1e-10, inner_rel_tol = 0;
 };
 
 struct SweepResult {
@@ -237,6 +254,7 @@ struct SweepResult {
     // next guess
     double t_phase[6] = {0, 0, 0, 0, 0, 0};
     long long plan_builds = 0, plan_hits = 0;  // work lists built / replayed from the plan caches
+    long long sigma_lo_calls = 0, refinements = 0;  // reduced-precision applications, FP64 residual restarts
 };
 
 class Engine {
@@ -297,6 +315,9 @@ class Engine {
     Two xlay_, last_lay_;
     double cg_tol2_ = 1e-20;
     int cg_max_ = 500;
+    int precision_ = 0;
+    double inner_tol2_ = 0;
+    DevBuf lf_, rf_, pf_, qf_;  // FP32 copies: environments of the window, direction, product
     std::vector<StepRecord> trace_;
     SweepResult res_;
     std::vector<std::vector<double>> psi1_guess_;

@@ -147,6 +147,152 @@ __global__ __launch_bounds__(256) void k_axpy_grouped(Bases bs, const AxpyGroup*
     }
 }
 
+// ------------------------------------------------- reduced-precision sigma
+// The same work lists, run on FP32 copies of the operands (slot bases point
+// at float arrays with the same element offsets).  Mode 1: FP32 MFMA
+// (v_mfma_f32_16x16x4f32).  Mode 2: BF16x3 - each FP32 operand is split
+// into a rounded BF16 head and a BF16 tail (the rounding error of the head),
+// and a.b is taken as head.head + head.tail + tail.head on the BF16 MFMA
+// (v_mfma_f32_16x16x16bf16_1k), accumulated in FP32; the dropped tail.tail
+// term and the tails' own rounding leave about 2^-16 relative error.
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef short s4 __attribute__((ext_vector_type(4)));
+
+// BF16 bits of x rounded to nearest even (finite x), and the BF16 bits of
+// the remainder x - head.
+__device__ inline void bf16_split(float x, short& head, short& tail) {
+    uint32_t u = __float_as_uint(x);
+    const uint32_t h = (u + 0x7FFFu + ((u >> 16) & 1u)) & 0xFFFF0000u;
+    head = (short)(h >> 16);
+    const float rest = x - __uint_as_float(h);
+    uint32_t v = __float_as_uint(rest);
+    v = v + 0x7FFFu + ((v >> 16) & 1u);
+    tail = (short)(v >> 16);
+}
+
+template <int MODE>
+__global__ __launch_bounds__(256) void k_gemm_grouped_lo(BasesF bs, const GemmGroup* __restrict__ G, int ngroups,
+                                                         const GemmTerm* __restrict__ T, int ntiles) {
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int tile = blockIdx.x * 4 + wave;
+    if (tile >= ntiles) return;
+    int lo = 0, hi = ngroups - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (G[mid].tile0 <= tile) lo = mid;
+        else hi = mid - 1;
+    }
+    const GemmGroup g = G[lo];
+    const int tiles_n = (g.n + GEMM_TILE - 1) / GEMM_TILE;
+    const int t = tile - g.tile0;
+    const int row0 = (t / tiles_n) * GEMM_TILE, col0 = (t % tiles_n) * GEMM_TILE;
+    const int li = lane & 15, lk = lane >> 4;
+    const int ar = row0 + li, bc = col0 + li;
+    const bool aok = ar < g.m, bok = bc < g.n;
+    f4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+    for (int ti = 0; ti < g.nterms; ++ti) {
+        const GemmTerm tm = T[g.term0 + ti];
+        const float* A = bs.p[tm.sa] + tm.oa;
+        const float* B = bs.p[tm.sb] + tm.ob;
+        const float* pa = tm.transA ? A + ar : A + (size_t)ar * tm.lda;
+        const size_t sa = tm.transA ? (size_t)tm.lda : 1;
+        const float* pb = tm.transB ? B + (size_t)bc * tm.ldb : B + bc;
+        const size_t sb = tm.transB ? 1 : (size_t)tm.ldb;
+        const float alpha = (float)tm.alpha;
+        const int k = tm.k;
+        if (MODE == 1) {
+            // lane holds op(A)[row li][k0 + lk + 4u], op(B)[k0 + lk + 4u][col li]
+            int k0 = 0;
+            for (; k0 + 16 <= k; k0 += 16) {
+                float a[4], b[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const size_t kk = (size_t)(k0 + 4 * u + lk);
+                    a[u] = aok ? pa[kk * sa] : 0.0f;
+                    b[u] = bok ? pb[kk * sb] : 0.0f;
+                }
+#pragma unroll
+                for (int u = 0; u < 4; ++u) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a[u], alpha * b[u], acc, 0, 0, 0);
+            }
+            for (; k0 < k; k0 += 4) {
+                const int kk = k0 + lk;
+                const float a = (aok && kk < k) ? pa[(size_t)kk * sa] : 0.0f;
+                const float b = (bok && kk < k) ? pb[(size_t)kk * sb] : 0.0f;
+                acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a, alpha * b, acc, 0, 0, 0);
+            }
+        } else {
+            // lane holds op(A)[row li][k0 + 4 lk + u], op(B)[k0 + 4 lk + u][col li], u < 4
+            for (int k0 = 0; k0 < k; k0 += 16) {
+                s4 ah, at, bh, bt;
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const int kk = k0 + 4 * lk + u;
+                    const float a = (aok && kk < k) ? pa[(size_t)kk * sa] : 0.0f;
+                    const float b = (bok && kk < k) ? alpha * pb[(size_t)kk * sb] : 0.0f;
+                    short h, tl;
+                    bf16_split(a, h, tl);
+                    ah[u] = h;
+                    at[u] = tl;
+                    bf16_split(b, h, tl);
+                    bh[u] = h;
+                    bt[u] = tl;
+                }
+                acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(at, bh, acc, 0, 0, 0);
+                acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, bt, acc, 0, 0, 0);
+                acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, bh, acc, 0, 0, 0);
+            }
+        }
+    }
+    // accumulator register e of a lane holds D[4 (lane / 16) + e][lane % 16]
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        const int gi = row0 + 4 * lk + e, gj = col0 + li;
+        if (gi < g.m && gj < g.n) {
+            float* c = bs.p[g.sc] + g.oc + (size_t)gi * g.ldc + gj;
+            *c = g.accumulate ? *c + acc[e] : acc[e];
+        }
+    }
+}
+
+__global__ __launch_bounds__(256) void k_axpy_grouped_lo(BasesF bs, const AxpyGroup* __restrict__ G,
+                                                         const AxpyTerm* __restrict__ T) {
+    const AxpyGroup g = G[blockIdx.x];
+    float* dst = bs.p[g.sd] + g.od;
+    const int total = g.m * g.n, di = blockDim.x / g.n, dj = blockDim.x - di * g.n;
+    int i = threadIdx.x / g.n, j = threadIdx.x - i * g.n;
+    for (int e = threadIdx.x; e < total; e += blockDim.x) {
+        float s = g.accumulate ? dst[(size_t)i * g.ldd + j] : 0.0f;
+        int t = 0;
+        for (; t + 8 <= g.nterms; t += 8) {
+            float v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const AxpyTerm tm = T[g.term0 + t + u];
+                const float* src = bs.p[tm.ss] + tm.os;
+                v[u] = (float)tm.alpha * (tm.trans ? src[(size_t)j * tm.lds + i] : src[(size_t)i * tm.lds + j]);
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) s += v[u];
+        }
+        for (; t < g.nterms; ++t) {
+            const AxpyTerm tm = T[g.term0 + t];
+            const float* src = bs.p[tm.ss] + tm.os;
+            s += (float)tm.alpha * (tm.trans ? src[(size_t)j * tm.lds + i] : src[(size_t)i * tm.lds + j]);
+        }
+        dst[(size_t)i * g.ldd + j] = s;
+        i += di;
+        j += dj;
+        if (j >= g.n) {
+            j -= g.n;
+            ++i;
+        }
+    }
+}
+
+__global__ __launch_bounds__(256) void k_to_f32(float* __restrict__ dst, const double* __restrict__ src, size_t n) {
+    for (size_t e = (size_t)blockIdx.x * 256 + threadIdx.x; e < n; e += (size_t)gridDim.x * 256) dst[e] = (float)src[e];
+}
+
 // ------------------------------------------------------------------- DIAG
 __global__ __launch_bounds__(256) void k_diag_grouped(Bases bs, const DiagGroup* __restrict__ G,
                                                       const DiagTerm* __restrict__ T) {
@@ -768,6 +914,30 @@ __global__ __launch_bounds__(RED_THREADS) void k_cg_direction(double* p, const d
         p[e] = z[e] + beta * p[e];
 }
 
+// reduced-precision sigma: the direction also goes out as FP32 ...
+__global__ __launch_bounds__(RED_THREADS) void k_cg_direction_lo(double* p, float* pf, const double* z, size_t n,
+                                                                 const double* scal, int rz_cur, int rz_new) {
+    const double den = scal[rz_cur];
+    const double beta = den != 0.0 ? scal[rz_new] / den : 0.0;
+    for (size_t e = (size_t)blockIdx.x * RED_THREADS + threadIdx.x; e < n; e += (size_t)gridDim.x * RED_THREADS) {
+        const double v = z[e] + beta * p[e];
+        p[e] = v;
+        pf[e] = (float)v;
+    }
+}
+
+// ... and its FP32 product comes back as q = qf - shift p with p.q in FP64
+__global__ __launch_bounds__(RED_THREADS) void k_shift_dot_lo(double* q, const float* qf, const double* p,
+                                                              double shift, size_t n, double* part, double* scal) {
+    double s = 0.0;
+    for (size_t e = (size_t)blockIdx.x * RED_THREADS + threadIdx.x; e < n; e += (size_t)gridDim.x * RED_THREADS) {
+        const double qv = (double)qf[e] - shift * p[e];
+        q[e] = qv;
+        s += p[e] * qv;
+    }
+    reduce_rows<1>({s}, part, scal, {(int)S_PQ});
+}
+
 __global__ __launch_bounds__(RED_THREADS) void k_axpby(double* y, const double* x, double a, double b, size_t n) {
     for (size_t e = (size_t)blockIdx.x * RED_THREADS + threadIdx.x; e < n; e += (size_t)gridDim.x * RED_THREADS)
         y[e] = a * x[e] + b * y[e];
@@ -1139,6 +1309,44 @@ void cg_direction(double* p, const double* z, size_t n, const double* scal, int 
     const int nb = n_blocks(n);
     launch(K_VEC, 2.0 * n, 24.0 * n, k_cg_direction, dim3(nb), dim3(RED_THREADS), 0, p, z, n, scal, rz_cur, rz_new);
     check(hipGetLastError(), "cg_direction");
+}
+void cg_direction_lo(double* p, float* pf, const double* z, size_t n, const double* scal, int rz_cur, int rz_new) {
+    const int nb = n_blocks(n);
+    launch(K_VEC, 2.0 * n, 28.0 * n, k_cg_direction_lo, dim3(nb), dim3(RED_THREADS), 0, p, pf, z, n, scal, rz_cur,
+           rz_new);
+    check(hipGetLastError(), "cg_direction_lo");
+}
+void cg_shift_dot_lo(double* q, const float* qf, const double* p, double shift, size_t n, double* scal,
+                     double* partials) {
+    const int nb = n_blocks(n);
+    launch(K_VEC, 4.0 * n, 20.0 * n, k_shift_dot_lo, dim3(nb), dim3(RED_THREADS), 0, q, qf, p, shift, n, partials,
+           scal);
+    check(hipGetLastError(), "cg_shift_dot_lo");
+}
+void to_f32(float* dst, const double* src, size_t n) {
+    if (n == 0) return;
+    const int nb = (int)std::min<size_t>((n + 255) / 256, 2048);
+    launch(K_VEC, 0.0, 12.0 * n, k_to_f32, dim3(nb), dim3(256), 0, dst, src, n);
+    check(hipGetLastError(), "to_f32");
+}
+void gemm_grouped_lo(const BasesF& b, int mode, const GemmGroup* groups, int ngroups, const GemmTerm* terms,
+                     int ntiles, double flops, double bytes) {
+    if (ntiles <= 0) return;
+    if (mode == 1)
+        launch(K_GEMM_LO, flops, bytes, k_gemm_grouped_lo<1>, dim3((ntiles + 3) / 4), dim3(256), 0, b, groups,
+               ngroups, terms, ntiles);
+    else if (mode == 2)
+        launch(K_GEMM_LO, flops, bytes, k_gemm_grouped_lo<2>, dim3((ntiles + 3) / 4), dim3(256), 0, b, groups,
+               ngroups, terms, ntiles);
+    else
+        throw Error{MPSPT_E_ARG, "reduced-precision GEMM mode must be 1 (FP32) or 2 (BF16x3)"};
+    check(hipGetLastError(), "k_gemm_grouped_lo");
+}
+void axpy_grouped_lo(const BasesF& b, const AxpyGroup* groups, int ngroups, const AxpyTerm* terms, double flops,
+                     double bytes) {
+    if (ngroups <= 0) return;
+    launch(K_AXPY_LO, flops, bytes, k_axpy_grouped_lo, dim3(ngroups), dim3(256), 0, b, groups, terms);
+    check(hipGetLastError(), "k_axpy_grouped_lo");
 }
 void davidson_precond(double* t, const double* r, const double* d, double theta, size_t n) {
     if (!n) return;

@@ -35,7 +35,8 @@ class MPSPTError(RuntimeError):
 class SweepParams(C.Structure):
     _fields_ = [("M1", C.c_int32), ("n_sweeps", C.c_int32), ("max_sweeps", C.c_int32),
                 ("e_tol", C.c_double), ("cg_rel_tol", C.c_double), ("cg_max_iter", C.c_int32),
-                ("compute_e3", C.c_int32), ("precond", C.c_int32)]
+                ("compute_e3", C.c_int32), ("precond", C.c_int32), ("precision", C.c_int32),
+                ("inner_rel_tol", C.c_double)]
 
 
 class Result(C.Structure):
@@ -45,7 +46,8 @@ class Result(C.Structure):
                 ("cg_iters", C.c_int64), ("sigma_calls", C.c_int64),
                 ("sigma_flops", C.c_double), ("sigma_bytes", C.c_double),
                 ("t_total_s", C.c_double), ("flags", C.c_int32), ("t_phase", C.c_double * 6),
-                ("plan_builds", C.c_int64), ("plan_hits", C.c_int64)]
+                ("plan_builds", C.c_int64), ("plan_hits", C.c_int64),
+                ("sigma_lo_calls", C.c_int64), ("refinements", C.c_int64)]
 
 
 _lib = None
@@ -203,8 +205,10 @@ class Context:
                                                 qn.ctypes.data_as(C.POINTER(C.c_int32)), ptrs))
 
     def sweep(self, M1, n_sweeps=0, max_sweeps=10, e_tol=1e-9, cg_rel_tol=1e-10, cg_max_iter=500,
-              compute_e3=True, precond=0):
-        p = SweepParams(M1, n_sweeps, max_sweeps, e_tol, cg_rel_tol, cg_max_iter, int(bool(compute_e3)), int(precond))
+              compute_e3=True, precond=0, precision=0, inner_rel_tol=0.0):
+        """precision: 0 FP64, 1 FP32, 2 BF16x3 sigma inside CG (FP64 refinement)."""
+        p = SweepParams(M1, n_sweeps, max_sweeps, e_tol, cg_rel_tol, cg_max_iter, int(bool(compute_e3)), int(precond),
+                        int(precision), float(inner_rel_tol))
         r = Result()
         self._ok(self.lib.mpspt_sweep(self.h, C.byref(p), C.byref(r)))
         out = {f: getattr(r, f) for f, _ in Result._fields_}
@@ -262,7 +266,7 @@ class Context:
         self._ok(self.lib.mpspt_profile(self.h, int(bool(enable))))
 
     KERNELS = {0: "k_gemm_grouped", 1: "k_axpy_grouped", 2: "k_eig_reduce", 3: "k_diag_grouped", 4: "k_eig_vectors",
-               5: "vector kernels"}
+               5: "vector kernels", 6: "k_gemm_grouped_lo", 7: "k_axpy_grouped_lo"}
 
     def kernel_stats(self, kind):
         s, n, f, b = C.c_double(), C.c_int64(), C.c_double(), C.c_double()
