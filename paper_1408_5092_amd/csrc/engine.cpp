@@ -226,32 +226,52 @@ TwoOp make_twoop(const MPO& m, int i) {
     O.nout = m.dims[i + 2];
     const auto& W1 = m.W[i];
     const auto& W2 = m.W[i + 1];
-    std::vector<std::vector<int>> in_mid(m.dims[i + 1]), out_mid(m.dims[i + 1]);
+    // W2 entries grouped by output channel, each group in (middle channel, entry) order
+    std::vector<std::vector<int>> by_out(O.nout);
+    for (size_t e = 0; e < W2.size(); ++e) by_out[W2[e].cout].push_back((int)e);
+    std::vector<std::vector<int>> in_mid(m.dims[i + 1]);
     for (size_t e = 0; e < W1.size(); ++e) in_mid[W1[e].cout].push_back((int)e);
-    for (size_t e = 0; e < W2.size(); ++e) out_mid[W2[e].cin].push_back((int)e);
-    std::map<std::tuple<int, int, int, int>, double> acc;  // (w'*16+s1'*4+s2', w, s1, s2)
-    for (int mid = 0; mid < m.dims[i + 1]; ++mid)
-        for (int a : in_mid[mid])
-            for (int b : out_mid[mid]) {
+    // dense accumulator over (s1' s2', w, s1 s2) for one output channel w'
+    const size_t row = (size_t)O.nin * 16;
+    std::vector<double> acc(16 * row, 0.0);
+    std::vector<char> hit(16 * row, 0);
+    std::vector<size_t> touched;
+    O.by_out.assign((size_t)O.nout * 16, {});
+    for (int wo = 0; wo < O.nout; ++wo) {
+        auto& list = by_out[wo];
+        std::stable_sort(list.begin(), list.end(), [&](int a, int b) { return W2[a].cin < W2[b].cin; });
+        touched.clear();
+        for (int b : list) {
+            const MPOEntry& e2 = W2[b];
+            for (int a : in_mid[e2.cin]) {
                 const MPOEntry& e1 = W1[a];
-                const MPOEntry& e2 = W2[b];
                 for (int s1p = 0; s1p < 4; ++s1p)
                     for (int s1 = 0; s1 < 4; ++s1) {
-                        double v1 = e1.m[s1p * 4 + s1];
+                        const double v1 = e1.m[s1p * 4 + s1];
                         if (v1 == 0.0) continue;
                         for (int s2p = 0; s2p < 4; ++s2p)
                             for (int s2 = 0; s2 < 4; ++s2) {
-                                double v2 = e2.m[s2p * 4 + s2];
+                                const double v2 = e2.m[s2p * 4 + s2];
                                 if (v2 == 0.0) continue;
-                                acc[{e2.cout * 16 + s1p * 4 + s2p, e1.cin, s1, s2}] += v1 * v2;
+                                const size_t k = (size_t)(s1p * 4 + s2p) * row + (size_t)e1.cin * 16 + s1 * 4 + s2;
+                                if (!hit[k]) {
+                                    hit[k] = 1;
+                                    touched.push_back(k);
+                                }
+                                acc[k] += v1 * v2;
                             }
                     }
             }
-    O.by_out.assign((size_t)O.nout * 16, {});
-    for (auto& kv : acc) {
-        if (kv.second == 0.0) continue;
-        O.by_out[std::get<0>(kv.first)].push_back(
-            {std::get<1>(kv.first), std::get<2>(kv.first), std::get<3>(kv.first), kv.second});
+        }
+        std::sort(touched.begin(), touched.end());
+        for (size_t k : touched) {
+            const int sp = (int)(k / row);
+            const int rest = (int)(k % row);
+            if (acc[k] != 0.0)
+                O.by_out[(size_t)wo * 16 + sp].push_back({rest / 16, (rest % 16) / 4, rest % 4, acc[k]});
+            acc[k] = 0.0;
+            hit[k] = 0;
+        }
     }
     return O;
 }
@@ -630,7 +650,7 @@ void Engine::build_mpos() {
     clear_plans();
     mpo_h0_ = build_mpo(OpKind::H0, k_a_, k_v_, h_, eri_, eps_);
     mpo_v_ = build_mpo(OpKind::VPsi0, k_a_, k_v_, h_, eri_, eps_);
-    mpo_e3_ = build_mpo(OpKind::VPsi1, k_a_, k_v_, h_, eri_, eps_);
+    mpo_e3_ = MPO();  // built on first use (E3 only)
     twoop_cache_[0].clear();
     clear_plans();
     twoop_cache_[1].clear();
@@ -1664,6 +1684,7 @@ void Engine::next_guess(int i, bool forward, Site& C) {
 }
 
 double Engine::e3_final(int window) {
+    if (mpo_e3_.n == 0) mpo_e3_ = build_mpo(OpKind::VPsi1, k_a_, k_v_, h_, eri_, eps_);
     const MPO& mf = mpo_e3_;
     Env R = trivial_env(A_[n_ - 1].R, A_[n_ - 1].R);
     for (int j = n_ - 1; j >= window + 2; --j) {

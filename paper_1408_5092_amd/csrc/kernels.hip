@@ -43,24 +43,31 @@ constexpr int RED_THREADS = 256;
 typedef double d4 __attribute__((ext_vector_type(4)));
 
 // ------------------------------------------------------------------- GEMM
-// One wave per 16 x 16 output tile (four tiles per workgroup, possibly of
-// different groups), no LDS and no barriers: each lane loads its MFMA
-// operands straight from global memory (A row lane%16 / B column lane%16,
-// k = lane/16 + 4 s), four k-steps of loads in flight per iteration, so a
-// group's terms run back to back without synchronisation.  Rows, columns
-// and k beyond the block are loaded as zeros.
-__global__ __launch_bounds__(256) void k_gemm_grouped(Bases bs, const GemmGroup* __restrict__ G, int ngroups,
-                                                      const GemmTerm* __restrict__ T, int ntiles) {
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int tile = blockIdx.x * 4 + wave;
-    if (tile >= ntiles) return;
+// One workgroup per 16 x 16 output tile.  The tile's k range - every term of
+// its group, in list order, cut into chunks of 16 - is dealt round-robin to
+// the four waves (chunk c to wave c % 4), so the dependent chain of loads
+// and MFMAs behind one tile is a quarter as long; each wave keeps the loads
+// of two chunks in flight.  No LDS staging: each lane loads its MFMA operands
+// straight from global memory (A row lane%16 / B column lane%16, k = lane/16
+// + 4 s).  Rows, columns and k beyond the block are loaded as zeros.  The
+// four partial tiles are added in wave order through LDS, so the result is
+// deterministic.
+__device__ inline int find_group(const GemmGroup* __restrict__ G, int ngroups, int tile) {
     int lo = 0, hi = ngroups - 1;
     while (lo < hi) {
         const int mid = (lo + hi + 1) >> 1;
         if (G[mid].tile0 <= tile) lo = mid;
         else hi = mid - 1;
     }
-    const GemmGroup g = G[lo];
+    return lo;
+}
+
+__global__ __launch_bounds__(256) void k_gemm_grouped(Bases bs, const GemmGroup* __restrict__ G, int ngroups,
+                                                      const GemmTerm* __restrict__ T, int ntiles) {
+    __shared__ d4 part[3][64];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int tile = blockIdx.x;
+    const GemmGroup g = G[find_group(G, ngroups, tile)];
     const int tiles_n = (g.n + GEMM_TILE - 1) / GEMM_TILE;
     const int t = tile - g.tile0;
     const int row0 = (t / tiles_n) * GEMM_TILE, col0 = (t % tiles_n) * GEMM_TILE;
@@ -68,6 +75,7 @@ __global__ __launch_bounds__(256) void k_gemm_grouped(Bases bs, const GemmGroup*
     const int ar = row0 + li, bc = col0 + li;
     const bool aok = ar < g.m, bok = bc < g.n;
     d4 acc = {0.0, 0.0, 0.0, 0.0};
+    int chunk0 = 0;  // chunks of the earlier terms
     for (int ti = 0; ti < g.nterms; ++ti) {
         const GemmTerm tm = T[g.term0 + ti];
         // element (row, kk) of op(A) at pa[kk * sa]; element (kk, col) of op(B) at pb[kk * sb]
@@ -79,72 +87,121 @@ __global__ __launch_bounds__(256) void k_gemm_grouped(Bases bs, const GemmGroup*
         const size_t sb = tm.transB ? 1 : (size_t)tm.ldb;
         const double alpha = tm.alpha;
         const int k = tm.k;
-        int k0 = 0;
-        for (; k0 + 16 <= k; k0 += 16) {
-            double a[4], b[4];
+        const int nch = (k + 15) >> 4;
+        int c = (wave - (chunk0 & 3)) & 3;  // first chunk of this term that is ours
+        for (; c < nch; c += 8) {
+            double a[8], b[8];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const size_t kk = (size_t)(k0 + 4 * u + lk);
-                a[u] = aok ? pa[kk * sa] : 0.0;
-                b[u] = bok ? pb[kk * sb] : 0.0;
-            }
+            for (int h = 0; h < 2; ++h)
 #pragma unroll
-            for (int u = 0; u < 4; ++u) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u], alpha * b[u], acc, 0, 0, 0);
+                for (int u = 0; u < 4; ++u) {
+                    const int kk = (c + 4 * h) * 16 + 4 * u + lk;
+                    const bool in = kk < k;
+                    a[4 * h + u] = (aok && in) ? pa[(size_t)kk * sa] : 0.0;
+                    b[4 * h + u] = (bok && in) ? pb[(size_t)kk * sb] : 0.0;
+                }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u], alpha * b[u], acc, 0, 0, 0);
         }
-        for (; k0 < k; k0 += 4) {
-            const int kk = k0 + lk;
-            const double a = (aok && kk < k) ? pa[(size_t)kk * sa] : 0.0;
-            const double b = (bok && kk < k) ? pb[(size_t)kk * sb] : 0.0;
-            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, alpha * b, acc, 0, 0, 0);
-        }
+        chunk0 += nch;
     }
+    if (wave > 0) part[wave - 1][lane] = acc;
+    __syncthreads();
+    if (wave != 0) return;
+#pragma unroll
+    for (int w = 0; w < 3; ++w) acc += part[w][lane];
     // accumulator register e of a lane holds D[lane / 16 + 4 e][lane % 16]
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
         const int gi = row0 + lk + 4 * e, gj = col0 + li;
         if (gi < g.m && gj < g.n) {
-            double* c = bs.p[g.sc] + g.oc + (size_t)gi * g.ldc + gj;
-            *c = g.accumulate ? *c + acc[e] : acc[e];
+            double* cp = bs.p[g.sc] + g.oc + (size_t)gi * g.ldc + gj;
+            *cp = g.accumulate ? *cp + acc[e] : acc[e];
         }
     }
 }
 
 // ------------------------------------------------------------------- AXPY
-__global__ __launch_bounds__(256) void k_axpy_grouped(Bases bs, const AxpyGroup* __restrict__ G,
-                                                      const AxpyTerm* __restrict__ T) {
-    const AxpyGroup g = G[blockIdx.x];
-    double* dst = bs.p[g.sd] + g.od;
-    // element e = i n + j, advanced by the block size without dividing
-    const int total = g.m * g.n, di = blockDim.x / g.n, dj = blockDim.x - di * g.n;
-    int i = threadIdx.x / g.n, j = threadIdx.x - i * g.n;
-    for (int e = threadIdx.x; e < total; e += blockDim.x) {
-        double s = g.accumulate ? dst[(size_t)i * g.ldd + j] : 0.0;
-        // eight terms' loads in flight, added in term order
-        int t = 0;
-        for (; t + 8 <= g.nterms; t += 8) {
-            double v[8];
+// One workgroup per output block.  A block with fewer elements than threads
+// deals its terms round-robin to S = min(256 / elements, terms / 4) thread
+// sets (term t to set t % S); each thread sums its terms in list order with
+// eight loads in flight, and the S partial sums of an element are added in
+// set order through LDS, so the result is deterministic.
+template <typename R, typename BS>
+__device__ inline void axpy_block(const BS& bs, const AxpyGroup& g, const AxpyTerm* __restrict__ T, R* red) {
+    R* dst = bs.p[g.sd] + g.od;
+    const int total = g.m * g.n;
+    if (total <= 0) return;
+    const int S = total >= 256 ? 1 : max(1, min(256 / total, g.nterms / 4));
+    if (S == 1) {
+        // element e = i n + j, advanced by the block size without dividing
+        const int di = blockDim.x / g.n, dj = blockDim.x - di * g.n;
+        int i = threadIdx.x / g.n, j = threadIdx.x - i * g.n;
+        for (int e = threadIdx.x; e < total; e += blockDim.x) {
+            R s = g.accumulate ? dst[(size_t)i * g.ldd + j] : R(0);
+            int t = 0;
+            for (; t + 8 <= g.nterms; t += 8) {
+                R v[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    const AxpyTerm tm = T[g.term0 + t + u];
+                    const R* src = bs.p[tm.ss] + tm.os;
+                    v[u] = (R)tm.alpha * (tm.trans ? src[(size_t)j * tm.lds + i] : src[(size_t)i * tm.lds + j]);
+                }
+#pragma unroll
+                for (int u = 0; u < 8; ++u) s += v[u];
+            }
+            for (; t < g.nterms; ++t) {
+                const AxpyTerm tm = T[g.term0 + t];
+                const R* src = bs.p[tm.ss] + tm.os;
+                s += (R)tm.alpha * (tm.trans ? src[(size_t)j * tm.lds + i] : src[(size_t)i * tm.lds + j]);
+            }
+            dst[(size_t)i * g.ldd + j] = s;
+            i += di;
+            j += dj;
+            if (j >= g.n) {
+                j -= g.n;
+                ++i;
+            }
+        }
+        return;
+    }
+    const int e = threadIdx.x % total, set = threadIdx.x / total;
+    R s = R(0);
+    if (set < S) {
+        const int i = e / g.n, j = e - i * g.n;
+        int t = set;
+        for (; t + 7 * S < g.nterms; t += 8 * S) {
+            R v[8];
 #pragma unroll
             for (int u = 0; u < 8; ++u) {
-                const AxpyTerm tm = T[g.term0 + t + u];
-                const double* src = bs.p[tm.ss] + tm.os;
-                v[u] = tm.alpha * (tm.trans ? src[(size_t)j * tm.lds + i] : src[(size_t)i * tm.lds + j]);
+                const AxpyTerm tm = T[g.term0 + t + u * S];
+                const R* src = bs.p[tm.ss] + tm.os;
+                v[u] = (R)tm.alpha * (tm.trans ? src[(size_t)j * tm.lds + i] : src[(size_t)i * tm.lds + j]);
             }
 #pragma unroll
             for (int u = 0; u < 8; ++u) s += v[u];
         }
-        for (; t < g.nterms; ++t) {
+        for (; t < g.nterms; t += S) {
             const AxpyTerm tm = T[g.term0 + t];
-            const double* src = bs.p[tm.ss] + tm.os;
-            s += tm.alpha * (tm.trans ? src[(size_t)j * tm.lds + i] : src[(size_t)i * tm.lds + j]);
-        }
-        dst[(size_t)i * g.ldd + j] = s;
-        i += di;
-        j += dj;
-        if (j >= g.n) {
-            j -= g.n;
-            ++i;
+            const R* src = bs.p[tm.ss] + tm.os;
+            s += (R)tm.alpha * (tm.trans ? src[(size_t)j * tm.lds + i] : src[(size_t)i * tm.lds + j]);
         }
     }
+    red[threadIdx.x] = s;
+    __syncthreads();
+    if (threadIdx.x < total) {
+        const int i = e / g.n, j = e - i * g.n;
+        R acc = g.accumulate ? dst[(size_t)i * g.ldd + j] : R(0);
+        for (int q = 0; q < S; ++q) acc += red[q * total + e];
+        dst[(size_t)i * g.ldd + j] = acc;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_axpy_grouped(Bases bs, const AxpyGroup* __restrict__ G,
+                                                      const AxpyTerm* __restrict__ T) {
+    __shared__ double red[256];
+    axpy_block<double>(bs, G[blockIdx.x], T, red);
 }
 
 // ------------------------------------------------- reduced-precision sigma
@@ -170,19 +227,14 @@ __device__ inline void bf16_split(float x, short& head, short& tail) {
     tail = (short)(v >> 16);
 }
 
+// Same tiling and chunk schedule as k_gemm_grouped.
 template <int MODE>
 __global__ __launch_bounds__(256) void k_gemm_grouped_lo(BasesF bs, const GemmGroup* __restrict__ G, int ngroups,
                                                          const GemmTerm* __restrict__ T, int ntiles) {
+    __shared__ f4 part[3][64];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int tile = blockIdx.x * 4 + wave;
-    if (tile >= ntiles) return;
-    int lo = 0, hi = ngroups - 1;
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (G[mid].tile0 <= tile) lo = mid;
-        else hi = mid - 1;
-    }
-    const GemmGroup g = G[lo];
+    const int tile = blockIdx.x;
+    const GemmGroup g = G[find_group(G, ngroups, tile)];
     const int tiles_n = (g.n + GEMM_TILE - 1) / GEMM_TILE;
     const int t = tile - g.tile0;
     const int row0 = (t / tiles_n) * GEMM_TILE, col0 = (t % tiles_n) * GEMM_TILE;
@@ -190,6 +242,7 @@ __global__ __launch_bounds__(256) void k_gemm_grouped_lo(BasesF bs, const GemmGr
     const int ar = row0 + li, bc = col0 + li;
     const bool aok = ar < g.m, bok = bc < g.n;
     f4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+    int chunk0 = 0;
     for (int ti = 0; ti < g.nterms; ++ti) {
         const GemmTerm tm = T[g.term0 + ti];
         const float* A = bs.p[tm.sa] + tm.oa;
@@ -200,93 +253,66 @@ __global__ __launch_bounds__(256) void k_gemm_grouped_lo(BasesF bs, const GemmGr
         const size_t sb = tm.transB ? 1 : (size_t)tm.ldb;
         const float alpha = (float)tm.alpha;
         const int k = tm.k;
-        if (MODE == 1) {
-            // lane holds op(A)[row li][k0 + lk + 4u], op(B)[k0 + lk + 4u][col li]
-            int k0 = 0;
-            for (; k0 + 16 <= k; k0 += 16) {
-                float a[4], b[4];
+        const int nch = (k + 15) >> 4;
+        int c = (wave - (chunk0 & 3)) & 3;
+        for (; c < nch; c += 8) {
+            float a[8], b[8];
+            // MODE 1: lane holds op(A)[row li][16 c + lk + 4 u], op(B)[16 c + lk + 4 u][col li]
+            // MODE 2: lane holds op(A)[row li][16 c + 4 lk + u], op(B)[16 c + 4 lk + u][col li]
+#pragma unroll
+            for (int h = 0; h < 2; ++h)
 #pragma unroll
                 for (int u = 0; u < 4; ++u) {
-                    const size_t kk = (size_t)(k0 + 4 * u + lk);
-                    a[u] = aok ? pa[kk * sa] : 0.0f;
-                    b[u] = bok ? pb[kk * sb] : 0.0f;
+                    const int kk = (c + 4 * h) * 16 + (MODE == 1 ? 4 * u + lk : 4 * lk + u);
+                    const bool in = kk < k;
+                    a[4 * h + u] = (aok && in) ? pa[(size_t)kk * sa] : 0.0f;
+                    b[4 * h + u] = (bok && in) ? alpha * pb[(size_t)kk * sb] : 0.0f;
                 }
+            if (MODE == 1) {
 #pragma unroll
-                for (int u = 0; u < 4; ++u) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a[u], alpha * b[u], acc, 0, 0, 0);
-            }
-            for (; k0 < k; k0 += 4) {
-                const int kk = k0 + lk;
-                const float a = (aok && kk < k) ? pa[(size_t)kk * sa] : 0.0f;
-                const float b = (bok && kk < k) ? pb[(size_t)kk * sb] : 0.0f;
-                acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a, alpha * b, acc, 0, 0, 0);
-            }
-        } else {
-            // lane holds op(A)[row li][k0 + 4 lk + u], op(B)[k0 + 4 lk + u][col li], u < 4
-            for (int k0 = 0; k0 < k; k0 += 16) {
-                s4 ah, at, bh, bt;
+                for (int u = 0; u < 8; ++u) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a[u], b[u], acc, 0, 0, 0);
+            } else {
 #pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    const int kk = k0 + 4 * lk + u;
-                    const float a = (aok && kk < k) ? pa[(size_t)kk * sa] : 0.0f;
-                    const float b = (bok && kk < k) ? alpha * pb[(size_t)kk * sb] : 0.0f;
-                    short h, tl;
-                    bf16_split(a, h, tl);
-                    ah[u] = h;
-                    at[u] = tl;
-                    bf16_split(b, h, tl);
-                    bh[u] = h;
-                    bt[u] = tl;
+                for (int h = 0; h < 2; ++h) {
+                    s4 ah, at, bh, bt;
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        short hh, tl;
+                        bf16_split(a[4 * h + u], hh, tl);
+                        ah[u] = hh;
+                        at[u] = tl;
+                        bf16_split(b[4 * h + u], hh, tl);
+                        bh[u] = hh;
+                        bt[u] = tl;
+                    }
+                    acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(at, bh, acc, 0, 0, 0);
+                    acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, bt, acc, 0, 0, 0);
+                    acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, bh, acc, 0, 0, 0);
                 }
-                acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(at, bh, acc, 0, 0, 0);
-                acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, bt, acc, 0, 0, 0);
-                acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, bh, acc, 0, 0, 0);
             }
         }
+        chunk0 += nch;
     }
+    if (wave > 0) part[wave - 1][lane] = acc;
+    __syncthreads();
+    if (wave != 0) return;
+#pragma unroll
+    for (int w = 0; w < 3; ++w) acc += part[w][lane];
     // accumulator register e of a lane holds D[4 (lane / 16) + e][lane % 16]
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
         const int gi = row0 + 4 * lk + e, gj = col0 + li;
         if (gi < g.m && gj < g.n) {
-            float* c = bs.p[g.sc] + g.oc + (size_t)gi * g.ldc + gj;
-            *c = g.accumulate ? *c + acc[e] : acc[e];
+            float* cp = bs.p[g.sc] + g.oc + (size_t)gi * g.ldc + gj;
+            *cp = g.accumulate ? *cp + acc[e] : acc[e];
         }
     }
 }
 
 __global__ __launch_bounds__(256) void k_axpy_grouped_lo(BasesF bs, const AxpyGroup* __restrict__ G,
                                                          const AxpyTerm* __restrict__ T) {
-    const AxpyGroup g = G[blockIdx.x];
-    float* dst = bs.p[g.sd] + g.od;
-    const int total = g.m * g.n, di = blockDim.x / g.n, dj = blockDim.x - di * g.n;
-    int i = threadIdx.x / g.n, j = threadIdx.x - i * g.n;
-    for (int e = threadIdx.x; e < total; e += blockDim.x) {
-        float s = g.accumulate ? dst[(size_t)i * g.ldd + j] : 0.0f;
-        int t = 0;
-        for (; t + 8 <= g.nterms; t += 8) {
-            float v[8];
-#pragma unroll
-            for (int u = 0; u < 8; ++u) {
-                const AxpyTerm tm = T[g.term0 + t + u];
-                const float* src = bs.p[tm.ss] + tm.os;
-                v[u] = (float)tm.alpha * (tm.trans ? src[(size_t)j * tm.lds + i] : src[(size_t)i * tm.lds + j]);
-            }
-#pragma unroll
-            for (int u = 0; u < 8; ++u) s += v[u];
-        }
-        for (; t < g.nterms; ++t) {
-            const AxpyTerm tm = T[g.term0 + t];
-            const float* src = bs.p[tm.ss] + tm.os;
-            s += (float)tm.alpha * (tm.trans ? src[(size_t)j * tm.lds + i] : src[(size_t)i * tm.lds + j]);
-        }
-        dst[(size_t)i * g.ldd + j] = s;
-        i += di;
-        j += dj;
-        if (j >= g.n) {
-            j -= g.n;
-            ++i;
-        }
-    }
+    __shared__ float red[256];
+    axpy_block<float>(bs, G[blockIdx.x], T, red);
 }
 
 __global__ __launch_bounds__(256) void k_to_f32(float* __restrict__ dst, const double* __restrict__ src, size_t n) {
@@ -1231,8 +1257,7 @@ KernelStats profile_stats(int kind) {
 void gemm_grouped(const Bases& b, const GemmGroup* groups, int ngroups, const GemmTerm* terms, int ntiles,
                   double flops, double bytes) {
     if (ntiles <= 0) return;
-    launch(K_GEMM, flops, bytes, k_gemm_grouped, dim3((ntiles + 3) / 4), dim3(256), 0, b, groups, ngroups, terms,
-           ntiles);
+    launch(K_GEMM, flops, bytes, k_gemm_grouped, dim3(ntiles), dim3(256), 0, b, groups, ngroups, terms, ntiles);
     check(hipGetLastError(), "k_gemm_grouped");
 }
 void axpy_grouped(const Bases& b, const AxpyGroup* groups, int ngroups, const AxpyTerm* terms, double flops,
@@ -1333,11 +1358,11 @@ void gemm_grouped_lo(const BasesF& b, int mode, const GemmGroup* groups, int ngr
                      int ntiles, double flops, double bytes) {
     if (ntiles <= 0) return;
     if (mode == 1)
-        launch(K_GEMM_LO, flops, bytes, k_gemm_grouped_lo<1>, dim3((ntiles + 3) / 4), dim3(256), 0, b, groups,
-               ngroups, terms, ntiles);
+        launch(K_GEMM_LO, flops, bytes, k_gemm_grouped_lo<1>, dim3(ntiles), dim3(256), 0, b, groups, ngroups,
+               terms, ntiles);
     else if (mode == 2)
-        launch(K_GEMM_LO, flops, bytes, k_gemm_grouped_lo<2>, dim3((ntiles + 3) / 4), dim3(256), 0, b, groups,
-               ngroups, terms, ntiles);
+        launch(K_GEMM_LO, flops, bytes, k_gemm_grouped_lo<2>, dim3(ntiles), dim3(256), 0, b, groups, ngroups,
+               terms, ntiles);
     else
         throw Error{MPSPT_E_ARG, "reduced-precision GEMM mode must be 1 (FP32) or 2 (BF16x3)"};
     check(hipGetLastError(), "k_gemm_grouped_lo");
