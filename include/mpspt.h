@@ -196,19 +196,24 @@ mpspt_status mpspt_mlp_train_step(mpspt_ctx *ctx, const float *X, const float *t
 mpspt_status mpspt_harvest(mpspt_ctx *ctx, int32_t enable);
 mpspt_status mpspt_harvest_get(mpspt_ctx *ctx, int64_t cap, float *X, float *t, int64_t *n_out);
 
-/* Kernel timing: enable = 1 starts recording HIP events around every launch
- * on the context's stream (counters reset), 0 stops.  mpspt_kernel_stats
+/* Kernel timing: enable = N >= 1 starts recording the start and end of every
+ * launch with probability 1/N, per kernel kind, on the context's stream with
+ * HIP events (a fixed hash of the kind and the launch count decides, so the
+ * choice is reproducible and does not follow the period of the solver's
+ * launch pattern; counters reset; N = 1 records every launch, larger N keeps
+ * the recording's own launch overhead out of the timed work), 0 stops.  mpspt_kernel_stats
  * returns, for kind 0 = grouped GEMM (k_gemm_grouped), 1 = grouped block
  * axpy, 2 = tridiagonal reduction and eigenvalues (k_eig_reduce), 3 = Jacobi
  * diagonal, 4 = kept-subspace bases (k_eig_vectors), 5 = CG / Davidson
  * vector kernels, 6 = reduced-precision grouped GEMM (k_gemm_grouped_lo),
- * 7 = reduced-precision block axpy, the summed event time,
- * launch count and the algorithmic flops / bytes of those launches (flops
- * 2mnk per block product; bytes: every operand block read once and every
- * output block written once).  Waits for outstanding launches. */
+ * 7 = reduced-precision block axpy, the summed event time, the number of
+ * recorded launches and the algorithmic flops / bytes of those launches
+ * (flops 2mnk per block product; bytes: every operand block read once and
+ * every output block written once), and in *launches_all every launch of the
+ * kind while recording was on.  Waits for outstanding launches. */
 mpspt_status mpspt_profile(mpspt_ctx *ctx, int32_t enable);
 mpspt_status mpspt_kernel_stats(mpspt_ctx *ctx, int32_t kind, double *seconds, int64_t *launches,
-                                double *flops, double *bytes);
+                                double *flops, double *bytes, int64_t *launches_all);
 
 /* Per local solve of the last mpspt_sweep: running E2, CG iterations,
  * discarded weight, seconds since the sweep started.  Up to cap entries;

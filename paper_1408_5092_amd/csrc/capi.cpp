@@ -261,7 +261,10 @@ mpspt_status mpspt_sweep(mpspt_ctx* ctx, const mpspt_sweep_params* params, mpspt
 
 mpspt_status mpspt_profile(mpspt_ctx* ctx, int32_t enable) {
     if (!ctx) return MPSPT_E_ARG;
-    return guard(ctx, [&] { mpspt::dev::profile_enable(enable != 0); });
+    return guard(ctx, [&] {
+        if (enable < 0) throw argerr("enable must be >= 0");
+        mpspt::dev::profile_enable(enable);
+    });
 }
 
 mpspt_status mpspt_precond_set(mpspt_ctx* ctx, const float* params, int32_t n) {
@@ -308,7 +311,7 @@ mpspt_status mpspt_harvest_get(mpspt_ctx* ctx, int64_t cap, float* X, float* t, 
 }
 
 mpspt_status mpspt_kernel_stats(mpspt_ctx* ctx, int32_t kind, double* seconds, int64_t* launches, double* flops,
-                                double* bytes) {
+                                double* bytes, int64_t* launches_all) {
     if (!ctx) return MPSPT_E_ARG;
     return guard(ctx, [&] {
         if (kind < 0 || kind >= mpspt::dev::K_COUNT) throw argerr("unknown kernel kind");
@@ -317,6 +320,7 @@ mpspt_status mpspt_kernel_stats(mpspt_ctx* ctx, int32_t kind, double* seconds, i
         if (launches) *launches = s.launches;
         if (flops) *flops = s.flops;
         if (bytes) *bytes = s.bytes;
+        if (launches_all) *launches_all = s.launches_all;
     });
 }
 

@@ -122,19 +122,27 @@ void event_wait(void* e);
 double now();  // host seconds
 
 // flops / bytes: algorithmic work of the launch, used only by the profiler
-void gemm_grouped(const Bases& b, const GemmGroup* groups, int ngroups, const GemmTerm* terms, int ntiles,
-                  double flops = 0, double bytes = 0);
+// tile_group[t]: the group of tile t.  split: one workgroup per tile with the
+// tile's k chunks spread over its four waves (long k chains), else one wave
+// per tile.
+void gemm_grouped(const Bases& b, const GemmGroup* groups, const int* tile_group, const GemmTerm* terms, int ntiles,
+                  bool split, double flops = 0, double bytes = 0);
 void axpy_grouped(const Bases& b, const AxpyGroup* groups, int ngroups, const AxpyTerm* terms, double flops = 0,
                   double bytes = 0);
 
 // Per-kernel timing with HIP events recorded on the library's stream.
 enum KernelKind { K_GEMM = 0, K_AXPY = 1, K_EIG = 2, K_DIAG = 3, K_EIGV = 4, K_VEC = 5, K_GEMM_LO = 6, K_AXPY_LO = 7,
                   K_COUNT = 8 };
+// seconds / flops / bytes / launches cover the recorded (sampled) launches;
+// launches_all counts every launch of the kind while recording was on.
 struct KernelStats {
     double seconds = 0, flops = 0, bytes = 0;
-    long long launches = 0;
+    long long launches = 0, launches_all = 0;
 };
-void profile_enable(bool on);          // resets the counters
+// every >= 1: record each launch with probability 1/every (a hash of the kind
+// and the launch count decides; 1: all); 0: off.
+// Resets the counters.
+void profile_enable(int every);
 KernelStats profile_stats(int kind);   // waits for outstanding launches
 void diag_grouped(const Bases& b, const DiagGroup* groups, int ngroups, const DiagTerm* terms);
 // nmax / kmax: largest n / k among the jobs.  Variant 0 of each kernel keeps
@@ -168,8 +176,8 @@ void cg_direction(double* p, const double* z, size_t n, const double* scal, int 
 void axpby(double* y, const double* x, double a, double b, size_t n);
 // Reduced-precision sigma (mode 1: FP32 MFMA, 2: BF16x3 split products with
 // FP32 accumulation) over the same work lists, on FP32 operand copies.
-void gemm_grouped_lo(const BasesF& b, int mode, const GemmGroup* groups, int ngroups, const GemmTerm* terms,
-                     int ntiles, double flops = 0, double bytes = 0);
+void gemm_grouped_lo(const BasesF& b, int mode, const GemmGroup* groups, const int* tile_group, const GemmTerm* terms,
+                     int ntiles, bool split, double flops = 0, double bytes = 0);
 void axpy_grouped_lo(const BasesF& b, const AxpyGroup* groups, int ngroups, const AxpyTerm* terms, double flops = 0,
                      double bytes = 0);
 void to_f32(float* dst, const double* src, size_t n);

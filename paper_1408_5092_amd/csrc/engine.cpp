@@ -335,11 +335,13 @@ void GemmBatch::term(const double* A, int lda, bool tA, const double* B, int ldb
 // into segments (at term boundaries, or inside a long term) that write
 // partial products to the batch's scratch; a grouped axpy then adds the
 // segments into C in order, so the result stays deterministic.
+// Launch shape: one workgroup per tile, k spread over its waves, once some
+// tile of the list has at least this many chunks of 16 in its k chain.
+constexpr long kWideChunks = 8;
+
 void GemmBatch::upload() {
     if (split_) {  // already laid out
-        dg_.upload(g_);
-        dt_.upload(t_);
-        red_.upload();
+        upload_lists();
         return;
     }
     split_ = true;
@@ -429,21 +431,36 @@ void GemmBatch::upload() {
     g_.swap(gs);
     t_.swap(ts);
     tiles_ = tiles;
+    upload_lists();
+}
+void GemmBatch::upload_lists() {
+    std::vector<int> tg((size_t)std::max(tiles_, 0));
+    long maxc = 0;
+    for (size_t gi = 0; gi < g_.size(); ++gi) {
+        const auto& g = g_[gi];
+        const int tl = ((g.m + kTile - 1) / kTile) * ((g.n + kTile - 1) / kTile);
+        for (int t = 0; t < tl; ++t) tg[(size_t)g.tile0 + t] = (int)gi;
+        long kc = 0;
+        for (int t = 0; t < g.nterms; ++t) kc += (t_[g.term0 + t].k + 15) / 16;
+        maxc = std::max(maxc, kc);
+    }
+    wide_ = maxc >= kWideChunks;
     dg_.upload(g_);
     dt_.upload(t_);
+    dtg_.upload(tg);
     red_.upload();
 }
 void GemmBatch::run() const {
     dev::Bases b = slots_.bases();
     b.p[kPartSlot] = part_.p;
-    if (tiles_ > 0) dev::gemm_grouped(b, dg_.p, (int)g_.size(), dt_.p, tiles_, flops_, bytes_);
+    if (tiles_ > 0) dev::gemm_grouped(b, dg_.p, dtg_.p, dt_.p, tiles_, wide_, flops_, bytes_);
     red_.run(b);
 }
 void GemmBatch::run_lo(const dev::BasesF& b, int mode) const {
     if (abs_) throw err(MPSPT_E_STATE, "reduced-precision work list refers outside its bound buffers");
     dev::BasesF c = b;
     c.p[kPartSlot] = reinterpret_cast<float*>(part_.p);
-    if (tiles_ > 0) dev::gemm_grouped_lo(c, mode, dg_.p, (int)g_.size(), dt_.p, tiles_, flops_, bytes_ / 2);
+    if (tiles_ > 0) dev::gemm_grouped_lo(c, mode, dg_.p, dtg_.p, dt_.p, tiles_, wide_, flops_, bytes_ / 2);
     red_.run_lo(c);
 }
 

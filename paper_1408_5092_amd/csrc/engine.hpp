@@ -189,8 +189,11 @@ class GemmBatch {
     std::vector<dev::GemmTerm> t_;
     DevArr<dev::GemmGroup> dg_;
     DevArr<dev::GemmTerm> dt_;
+    DevArr<int> dtg_;    // tile -> group
+    bool wide_ = false;  // launch shape: one workgroup per tile (long k chains)
     int tiles_ = 0;
     double flops_ = 0, bytes_ = 0;
+    void upload_lists();
     AxpyBatch red_;  // sums split-k partials into the outputs
     DevBuf part_;
     bool split_ = false;

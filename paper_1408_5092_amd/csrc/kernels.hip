@@ -1,9 +1,10 @@
 // gfx950 kernels of the MPS-PT engine and the host side of device.hpp.
 //
-// * k_gemm_grouped: output-stationary grouped FP64 GEMM on MFMA
-//   (v_mfma_f64_16x16x4f64).  A 256-thread workgroup owns one 32x32 tile of
-//   one output block and sums every term of that block in list order, so a
-//   block-sparse contraction is one launch and its result is deterministic.
+// * k_gemm_grouped / k_gemm_grouped_split: output-stationary grouped GEMM on
+//   MFMA over a work list of output blocks, each the sum of its terms in list
+//   order, so a block-sparse contraction is one launch and its result is
+//   deterministic (FP64; FP32 and BF16x3 instances for the reduced-precision
+//   sigma).
 // * k_axpy_grouped: linear combinations of dense blocks (MPO coefficients).
 // * k_diag_grouped: Jacobi diagonal of the effective operator.
 // * k_eig_tridiag: batched symmetric eigensolver (Householder tridiagonal
@@ -16,6 +17,7 @@
 #include <cmath>
 #include <algorithm>
 #include <cstdio>
+#include <cstring>
 #include <mutex>
 #include <string>
 #include <unordered_map>
@@ -43,82 +45,197 @@ constexpr int RED_THREADS = 256;
 typedef double d4 __attribute__((ext_vector_type(4)));
 
 // ------------------------------------------------------------------- GEMM
-// One workgroup per 16 x 16 output tile.  The tile's k range - every term of
-// its group, in list order, cut into chunks of 16 - is dealt round-robin to
-// the four waves (chunk c to wave c % 4), so the dependent chain of loads
-// and MFMAs behind one tile is a quarter as long; each wave keeps the loads
-// of two chunks in flight.  No LDS staging: each lane loads its MFMA operands
-// straight from global memory (A row lane%16 / B column lane%16, k = lane/16
-// + 4 s).  Rows, columns and k beyond the block are loaded as zeros.  The
-// four partial tiles are added in wave order through LDS, so the result is
-// deterministic.
-__device__ inline int find_group(const GemmGroup* __restrict__ G, int ngroups, int tile) {
-    int lo = 0, hi = ngroups - 1;
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (G[mid].tile0 <= tile) lo = mid;
-        else hi = mid - 1;
-    }
-    return lo;
+// Output-stationary grouped GEMM on MFMA.  A group is one output block; its
+// 16 x 16 tiles are numbered consecutively and tile_group maps a tile to its
+// group.  A tile sums every term of its group in list order, each term's k
+// range cut into chunks of 16.  Two launch shapes over the same lists:
+//   k_gemm_grouped:       one wave per tile (four tiles per workgroup), for
+//                         lists whose tiles have short k chains;
+//   k_gemm_grouped_split: one workgroup per tile, the chunks dealt
+//                         round-robin to the four waves (chunk c to wave
+//                         c % 4) and the partial tiles added in wave order
+//                         through LDS, for lists with long k chains.
+// No LDS staging of operands: each lane loads its MFMA operands straight from
+// global memory, two chunks in flight; rows, columns and k beyond the block
+// load as zeros.  Results are deterministic for either shape.
+// Element types: MODE 0 FP64 (v_mfma_f64_16x16x4f64), 1 FP32
+// (v_mfma_f32_16x16x4f32), 2 BF16x3 on FP32 data (three
+// v_mfma_f32_16x16x16bf16_1k products of head/tail-split operands).
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef short s4 __attribute__((ext_vector_type(4)));
+
+template <int MODE>
+struct GemmTypes {
+    typedef float R;
+    typedef f4 V;
+    typedef BasesF B;
+};
+template <>
+struct GemmTypes<0> {
+    typedef double R;
+    typedef d4 V;
+    typedef Bases B;
+};
+
+// BF16 bits of x rounded to nearest even (finite x), and the BF16 bits of
+// the remainder x - head.
+__device__ inline void bf16_split(float x, short& head, short& tail) {
+    uint32_t u = __float_as_uint(x);
+    const uint32_t h = (u + 0x7FFFu + ((u >> 16) & 1u)) & 0xFFFF0000u;
+    head = (short)(h >> 16);
+    const float rest = x - __uint_as_float(h);
+    uint32_t v = __float_as_uint(rest);
+    v = v + 0x7FFFu + ((v >> 16) & 1u);
+    tail = (short)(v >> 16);
 }
 
-__global__ __launch_bounds__(256) void k_gemm_grouped(Bases bs, const GemmGroup* __restrict__ G, int ngroups,
-                                                      const GemmTerm* __restrict__ T, int ntiles) {
-    __shared__ d4 part[3][64];
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int tile = blockIdx.x;
-    const GemmGroup g = G[find_group(G, ngroups, tile)];
-    const int tiles_n = (g.n + GEMM_TILE - 1) / GEMM_TILE;
-    const int t = tile - g.tile0;
-    const int row0 = (t / tiles_n) * GEMM_TILE, col0 = (t % tiles_n) * GEMM_TILE;
+// One wave's share of one tile: chunks c0, c0 + cs, c0 + 2 cs, ... of the
+// group's chunk sequence.
+template <int MODE>
+__device__ inline typename GemmTypes<MODE>::V gemm_tile(const typename GemmTypes<MODE>::B& bs, const GemmGroup& g,
+                                                        const GemmTerm* __restrict__ T, int row0, int col0,
+                                                        int lane, int c0, int cs) {
+    typedef typename GemmTypes<MODE>::R R;
+    typedef typename GemmTypes<MODE>::V V;
     const int li = lane & 15, lk = lane >> 4;
     const int ar = row0 + li, bc = col0 + li;
     const bool aok = ar < g.m, bok = bc < g.n;
-    d4 acc = {0.0, 0.0, 0.0, 0.0};
+    V acc = {R(0), R(0), R(0), R(0)};
     int chunk0 = 0;  // chunks of the earlier terms
     for (int ti = 0; ti < g.nterms; ++ti) {
         const GemmTerm tm = T[g.term0 + ti];
         // element (row, kk) of op(A) at pa[kk * sa]; element (kk, col) of op(B) at pb[kk * sb]
-        const double* A = bs.p[tm.sa] + tm.oa;
-        const double* B = bs.p[tm.sb] + tm.ob;
-        const double* pa = tm.transA ? A + ar : A + (size_t)ar * tm.lda;
+        const R* A = bs.p[tm.sa] + tm.oa;
+        const R* B = bs.p[tm.sb] + tm.ob;
+        const R* pa = tm.transA ? A + ar : A + (size_t)ar * tm.lda;
         const size_t sa = tm.transA ? (size_t)tm.lda : 1;
-        const double* pb = tm.transB ? B + (size_t)bc * tm.ldb : B + bc;
+        const R* pb = tm.transB ? B + (size_t)bc * tm.ldb : B + bc;
         const size_t sb = tm.transB ? 1 : (size_t)tm.ldb;
-        const double alpha = tm.alpha;
+        const R alpha = (R)tm.alpha;
         const int k = tm.k;
         const int nch = (k + 15) >> 4;
-        int c = (wave - (chunk0 & 3)) & 3;  // first chunk of this term that is ours
-        for (; c < nch; c += 8) {
-            double a[8], b[8];
+        // first chunk of this term that is ours
+        int c = cs == 1 ? 0 : (c0 - chunk0 % cs + cs) % cs;
+        for (; c < nch; c += 2 * cs) {
+            R a[8], b[8];
+            // MODE 0/1: lane holds op(A)[row li][16 c + lk + 4 u], op(B)[16 c + lk + 4 u][col li]
+            // MODE 2:   lane holds op(A)[row li][16 c + 4 lk + u], op(B)[16 c + 4 lk + u][col li]
 #pragma unroll
             for (int h = 0; h < 2; ++h)
 #pragma unroll
                 for (int u = 0; u < 4; ++u) {
-                    const int kk = (c + 4 * h) * 16 + 4 * u + lk;
+                    const int kk = (c + h * cs) * 16 + (MODE == 2 ? 4 * lk + u : 4 * u + lk);
                     const bool in = kk < k;
-                    a[4 * h + u] = (aok && in) ? pa[(size_t)kk * sa] : 0.0;
-                    b[4 * h + u] = (bok && in) ? pb[(size_t)kk * sb] : 0.0;
+                    a[4 * h + u] = (aok && in) ? pa[(size_t)kk * sa] : R(0);
+                    b[4 * h + u] = (bok && in) ? alpha * pb[(size_t)kk * sb] : R(0);
                 }
+            if constexpr (MODE == 0) {
 #pragma unroll
-            for (int u = 0; u < 8; ++u) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u], alpha * b[u], acc, 0, 0, 0);
+                for (int u = 0; u < 8; ++u) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u], b[u], acc, 0, 0, 0);
+            } else if constexpr (MODE == 1) {
+#pragma unroll
+                for (int u = 0; u < 8; ++u) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a[u], b[u], acc, 0, 0, 0);
+            } else {
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    s4 ah, at, bh, bt;
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        short hh, tl;
+                        bf16_split(a[4 * h + u], hh, tl);
+                        ah[u] = hh;
+                        at[u] = tl;
+                        bf16_split(b[4 * h + u], hh, tl);
+                        bh[u] = hh;
+                        bt[u] = tl;
+                    }
+                    acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(at, bh, acc, 0, 0, 0);
+                    acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, bt, acc, 0, 0, 0);
+                    acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, bh, acc, 0, 0, 0);
+                }
+            }
         }
         chunk0 += nch;
     }
+    return acc;
+}
+
+template <int MODE>
+__device__ inline void gemm_store(const typename GemmTypes<MODE>::B& bs, const GemmGroup& g, int row0, int col0,
+                                  int lane, const typename GemmTypes<MODE>::V& acc) {
+    typedef typename GemmTypes<MODE>::R R;
+    const int li = lane & 15, lk = lane >> 4;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        // accumulator register e of a lane holds D[lane/16 + 4 e][lane%16] (f64 MFMA)
+        // or D[4 (lane/16) + e][lane%16] (f32 and bf16 MFMA)
+        const int gi = row0 + (MODE == 0 ? lk + 4 * e : 4 * lk + e), gj = col0 + li;
+        if (gi < g.m && gj < g.n) {
+            R* cp = bs.p[g.sc] + g.oc + (size_t)gi * g.ldc + gj;
+            *cp = g.accumulate ? *cp + acc[e] : acc[e];
+        }
+    }
+}
+
+template <int MODE>
+__device__ inline void gemm_wave_per_tile(const typename GemmTypes<MODE>::B& bs, const GemmGroup* __restrict__ G,
+                                          const int* __restrict__ TG, const GemmTerm* __restrict__ T, int ntiles) {
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int tile = blockIdx.x * 4 + wave;
+    if (tile >= ntiles) return;
+    const GemmGroup g = G[TG[tile]];
+    const int tiles_n = (g.n + GEMM_TILE - 1) / GEMM_TILE;
+    const int t = tile - g.tile0;
+    const int row0 = (t / tiles_n) * GEMM_TILE, col0 = (t % tiles_n) * GEMM_TILE;
+    const auto acc = gemm_tile<MODE>(bs, g, T, row0, col0, lane, 0, 1);
+    gemm_store<MODE>(bs, g, row0, col0, lane, acc);
+}
+
+template <int MODE>
+__device__ inline void gemm_split_tile(const typename GemmTypes<MODE>::B& bs, const GemmGroup* __restrict__ G,
+                                       const int* __restrict__ TG, const GemmTerm* __restrict__ T,
+                                       typename GemmTypes<MODE>::V (*part)[64]) {
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int tile = blockIdx.x;
+    const GemmGroup g = G[TG[tile]];
+    const int tiles_n = (g.n + GEMM_TILE - 1) / GEMM_TILE;
+    const int t = tile - g.tile0;
+    const int row0 = (t / tiles_n) * GEMM_TILE, col0 = (t % tiles_n) * GEMM_TILE;
+    auto acc = gemm_tile<MODE>(bs, g, T, row0, col0, lane, wave, 4);
     if (wave > 0) part[wave - 1][lane] = acc;
     __syncthreads();
     if (wave != 0) return;
 #pragma unroll
     for (int w = 0; w < 3; ++w) acc += part[w][lane];
-    // accumulator register e of a lane holds D[lane / 16 + 4 e][lane % 16]
-#pragma unroll
-    for (int e = 0; e < 4; ++e) {
-        const int gi = row0 + lk + 4 * e, gj = col0 + li;
-        if (gi < g.m && gj < g.n) {
-            double* cp = bs.p[g.sc] + g.oc + (size_t)gi * g.ldc + gj;
-            *cp = g.accumulate ? *cp + acc[e] : acc[e];
-        }
-    }
+    gemm_store<MODE>(bs, g, row0, col0, lane, acc);
+}
+
+__global__ __launch_bounds__(256) void k_gemm_grouped(Bases bs, const GemmGroup* __restrict__ G,
+                                                      const int* __restrict__ TG, const GemmTerm* __restrict__ T,
+                                                      int ntiles) {
+    gemm_wave_per_tile<0>(bs, G, TG, T, ntiles);
+}
+
+__global__ __launch_bounds__(256) void k_gemm_grouped_split(Bases bs, const GemmGroup* __restrict__ G,
+                                                            const int* __restrict__ TG,
+                                                            const GemmTerm* __restrict__ T) {
+    __shared__ d4 part[3][64];
+    gemm_split_tile<0>(bs, G, TG, T, part);
+}
+
+template <int MODE>
+__global__ __launch_bounds__(256) void k_gemm_grouped_lo(BasesF bs, const GemmGroup* __restrict__ G,
+                                                         const int* __restrict__ TG, const GemmTerm* __restrict__ T,
+                                                         int ntiles) {
+    gemm_wave_per_tile<MODE>(bs, G, TG, T, ntiles);
+}
+
+template <int MODE>
+__global__ __launch_bounds__(256) void k_gemm_grouped_lo_split(BasesF bs, const GemmGroup* __restrict__ G,
+                                                               const int* __restrict__ TG,
+                                                               const GemmTerm* __restrict__ T) {
+    __shared__ f4 part[3][64];
+    gemm_split_tile<MODE>(bs, G, TG, T, part);
 }
 
 // ------------------------------------------------------------------- AXPY
@@ -206,109 +323,8 @@ __global__ __launch_bounds__(256) void k_axpy_grouped(Bases bs, const AxpyGroup*
 
 // ------------------------------------------------- reduced-precision sigma
 // The same work lists, run on FP32 copies of the operands (slot bases point
-// at float arrays with the same element offsets).  Mode 1: FP32 MFMA
-// (v_mfma_f32_16x16x4f32).  Mode 2: BF16x3 - each FP32 operand is split
-// into a rounded BF16 head and a BF16 tail (the rounding error of the head),
-// and a.b is taken as head.head + head.tail + tail.head on the BF16 MFMA
-// (v_mfma_f32_16x16x16bf16_1k), accumulated in FP32; the dropped tail.tail
-// term and the tails' own rounding leave about 2^-16 relative error.
-typedef float f4 __attribute__((ext_vector_type(4)));
-typedef short s4 __attribute__((ext_vector_type(4)));
-
-// BF16 bits of x rounded to nearest even (finite x), and the BF16 bits of
-// the remainder x - head.
-__device__ inline void bf16_split(float x, short& head, short& tail) {
-    uint32_t u = __float_as_uint(x);
-    const uint32_t h = (u + 0x7FFFu + ((u >> 16) & 1u)) & 0xFFFF0000u;
-    head = (short)(h >> 16);
-    const float rest = x - __uint_as_float(h);
-    uint32_t v = __float_as_uint(rest);
-    v = v + 0x7FFFu + ((v >> 16) & 1u);
-    tail = (short)(v >> 16);
-}
-
-// Same tiling and chunk schedule as k_gemm_grouped.
-template <int MODE>
-__global__ __launch_bounds__(256) void k_gemm_grouped_lo(BasesF bs, const GemmGroup* __restrict__ G, int ngroups,
-                                                         const GemmTerm* __restrict__ T, int ntiles) {
-    __shared__ f4 part[3][64];
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int tile = blockIdx.x;
-    const GemmGroup g = G[find_group(G, ngroups, tile)];
-    const int tiles_n = (g.n + GEMM_TILE - 1) / GEMM_TILE;
-    const int t = tile - g.tile0;
-    const int row0 = (t / tiles_n) * GEMM_TILE, col0 = (t % tiles_n) * GEMM_TILE;
-    const int li = lane & 15, lk = lane >> 4;
-    const int ar = row0 + li, bc = col0 + li;
-    const bool aok = ar < g.m, bok = bc < g.n;
-    f4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
-    int chunk0 = 0;
-    for (int ti = 0; ti < g.nterms; ++ti) {
-        const GemmTerm tm = T[g.term0 + ti];
-        const float* A = bs.p[tm.sa] + tm.oa;
-        const float* B = bs.p[tm.sb] + tm.ob;
-        const float* pa = tm.transA ? A + ar : A + (size_t)ar * tm.lda;
-        const size_t sa = tm.transA ? (size_t)tm.lda : 1;
-        const float* pb = tm.transB ? B + (size_t)bc * tm.ldb : B + bc;
-        const size_t sb = tm.transB ? 1 : (size_t)tm.ldb;
-        const float alpha = (float)tm.alpha;
-        const int k = tm.k;
-        const int nch = (k + 15) >> 4;
-        int c = (wave - (chunk0 & 3)) & 3;
-        for (; c < nch; c += 8) {
-            float a[8], b[8];
-            // MODE 1: lane holds op(A)[row li][16 c + lk + 4 u], op(B)[16 c + lk + 4 u][col li]
-            // MODE 2: lane holds op(A)[row li][16 c + 4 lk + u], op(B)[16 c + 4 lk + u][col li]
-#pragma unroll
-            for (int h = 0; h < 2; ++h)
-#pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    const int kk = (c + 4 * h) * 16 + (MODE == 1 ? 4 * u + lk : 4 * lk + u);
-                    const bool in = kk < k;
-                    a[4 * h + u] = (aok && in) ? pa[(size_t)kk * sa] : 0.0f;
-                    b[4 * h + u] = (bok && in) ? alpha * pb[(size_t)kk * sb] : 0.0f;
-                }
-            if (MODE == 1) {
-#pragma unroll
-                for (int u = 0; u < 8; ++u) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a[u], b[u], acc, 0, 0, 0);
-            } else {
-#pragma unroll
-                for (int h = 0; h < 2; ++h) {
-                    s4 ah, at, bh, bt;
-#pragma unroll
-                    for (int u = 0; u < 4; ++u) {
-                        short hh, tl;
-                        bf16_split(a[4 * h + u], hh, tl);
-                        ah[u] = hh;
-                        at[u] = tl;
-                        bf16_split(b[4 * h + u], hh, tl);
-                        bh[u] = hh;
-                        bt[u] = tl;
-                    }
-                    acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(at, bh, acc, 0, 0, 0);
-                    acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, bt, acc, 0, 0, 0);
-                    acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, bh, acc, 0, 0, 0);
-                }
-            }
-        }
-        chunk0 += nch;
-    }
-    if (wave > 0) part[wave - 1][lane] = acc;
-    __syncthreads();
-    if (wave != 0) return;
-#pragma unroll
-    for (int w = 0; w < 3; ++w) acc += part[w][lane];
-    // accumulator register e of a lane holds D[4 (lane / 16) + e][lane % 16]
-#pragma unroll
-    for (int e = 0; e < 4; ++e) {
-        const int gi = row0 + 4 * lk + e, gj = col0 + li;
-        if (gi < g.m && gj < g.n) {
-            float* cp = bs.p[g.sc] + g.oc + (size_t)gi * g.ldc + gj;
-            *cp = g.accumulate ? *cp + acc[e] : acc[e];
-        }
-    }
-}
-
+// at float arrays with the same element offsets); the GEMMs are the MODE 1/2
+// instances above.
 __global__ __launch_bounds__(256) void k_axpy_grouped_lo(BasesF bs, const AxpyGroup* __restrict__ G,
                                                          const AxpyTerm* __restrict__ T) {
     __shared__ float red[256];
@@ -999,8 +1015,14 @@ struct Stream {
     // caching pool
     std::unordered_map<size_t, std::vector<void*>> free_blocks;
     std::unordered_map<void*, size_t> block_size;
-    // profiling
+    // pinned staging ring for host-to-device copies, and a pinned bounce
+    // buffer for small device-to-host copies (both allocated on first use)
+    char* stage = nullptr;
+    size_t stage_head = 0;
+    char* bounce = nullptr;
+    // profiling: every prof_every-th launch of each kind is recorded
     bool prof = false;
+    int prof_every = 1;
     std::vector<ProfRec> pending;
     std::vector<hipEvent_t> event_pool;
     KernelStats stats[K_COUNT];
@@ -1080,6 +1102,8 @@ void stream_destroy(Stream* s) {
         (void)hipEventDestroy(r.b);
     }
     for (hipEvent_t ev : s->event_pool) (void)hipEventDestroy(ev);
+    if (s->stage) (void)hipHostFree(s->stage);
+    if (s->bounce) (void)hipHostFree(s->bounce);
     // blocks still handed out (none once the engine is gone) stay with the runtime
     delete s;
     t_cur = prev == s ? nullptr : prev;
@@ -1138,15 +1162,53 @@ void trim() {
         }
     st.free_blocks.clear();
 }
+// Host-to-device copies go through a pinned ring: the source is copied into
+// the ring at once, and the DMA from the ring is ordered on the stream, so
+// the call never waits for earlier work (a pageable source would be staged
+// by the runtime, which can hold the host until the stream drains).  When
+// the ring wraps, the host waits for the stream once, so no region is
+// rewritten while a copy from it may still be pending.
+constexpr size_t kStageBytes = 32u << 20;
+constexpr size_t kBounceBytes = 1u << 20;
 void h2d(void* dst, const void* src, size_t bytes) {
     if (!bytes) return;
-    // ordered on the stream; pageable sources are staged by the runtime before it returns
-    check(hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, cur_stream()), "hipMemcpyAsync H2D");
+    Stream& st = cur();
+    const size_t need = (bytes + 255) & ~size_t(255);
+    if (need > kStageBytes / 4) {  // large one-off inputs: the runtime stages them
+        check(hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, st.stream), "hipMemcpyAsync H2D");
+        return;
+    }
+    if (!st.stage) {
+        void* p = nullptr;
+        check(hipHostMalloc(&p, kStageBytes, hipHostMallocDefault), "hipHostMalloc");
+        st.stage = static_cast<char*>(p);
+        st.stage_head = 0;
+    }
+    if (st.stage_head + need > kStageBytes) {
+        check(hipStreamSynchronize(st.stream), "hipStreamSynchronize");
+        st.stage_head = 0;
+    }
+    char* slot = st.stage + st.stage_head;
+    std::memcpy(slot, src, bytes);
+    st.stage_head += need;
+    check(hipMemcpyAsync(dst, slot, bytes, hipMemcpyHostToDevice, st.stream), "hipMemcpyAsync H2D");
 }
 void d2h(void* dst, const void* src, size_t bytes) {
     if (!bytes) return;
-    check(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, cur_stream()), "hipMemcpyAsync D2H");
-    check(hipStreamSynchronize(cur_stream()), "hipStreamSynchronize");
+    Stream& st = cur();
+    if (bytes <= kBounceBytes) {
+        if (!st.bounce) {
+            void* p = nullptr;
+            check(hipHostMalloc(&p, kBounceBytes, hipHostMallocDefault), "hipHostMalloc");
+            st.bounce = static_cast<char*>(p);
+        }
+        check(hipMemcpyAsync(st.bounce, src, bytes, hipMemcpyDeviceToHost, st.stream), "hipMemcpyAsync D2H");
+        check(hipStreamSynchronize(st.stream), "hipStreamSynchronize");
+        std::memcpy(dst, st.bounce, bytes);
+        return;
+    }
+    check(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, st.stream), "hipMemcpyAsync D2H");
+    check(hipStreamSynchronize(st.stream), "hipStreamSynchronize");
 }
 void d2d(void* dst, const void* src, size_t bytes) {
     if (!bytes) return;
@@ -1188,6 +1250,18 @@ double now() {
 // ------------------------------------------------------------ profiling
 namespace {
 
+// Whether launch number c of a kind is recorded: a hash of (kind, c), so the
+// one-in-every choice does not lock onto the period of a solver's launch
+// pattern (a fixed stride would time the same stage of every iteration).
+inline bool sampled(int kind, long long c, int every) {
+    if (every <= 1) return true;
+    uint64_t z = (uint64_t)c + 0x9E3779B97F4A7C15ull * (uint64_t)(kind + 1);
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    z ^= z >> 31;
+    return z % (uint64_t)every == 0;
+}
+
 hipEvent_t take_event() {
     auto& pool = cur().event_pool;
     if (!pool.empty()) {
@@ -1224,7 +1298,7 @@ void prof_flush() {
 template <typename F, typename... Args>
 void launch(int kind, double flops, double bytes, F kernel, dim3 grid, dim3 block, size_t shm, Args... args) {
     Stream& st = cur();
-    if (st.prof) {
+    if (st.prof && sampled(kind, st.stats[kind].launches_all++, st.prof_every)) {
         ProfRec r{kind, take_event(), take_event(), flops, bytes};
         hipExtLaunchKernelGGL(kernel, grid, block, (uint32_t)shm, st.stream, r.a, r.b, 0, args...);
         st.pending.push_back(r);
@@ -1239,10 +1313,12 @@ void launch(int kind, double flops, double bytes, F kernel, dim3 grid, dim3 bloc
 // external kernel trace can find the recorded window.
 __global__ void k_profile_mark(int on) {}
 
-void profile_enable(bool on) {
+void profile_enable(int every) {
     Stream& st = cur();
     if (st.prof) prof_flush();
+    const bool on = every > 0;
     st.prof = on;
+    st.prof_every = on ? every : 1;
     for (auto& s : st.stats) s = KernelStats();
     hipLaunchKernelGGL(k_profile_mark, dim3(1), dim3(64), 0, cur_stream(), on ? 1 : 0);
     check(hipGetLastError(), "k_profile_mark");
@@ -1254,10 +1330,14 @@ KernelStats profile_stats(int kind) {
     return cur().stats[kind];
 }
 
-void gemm_grouped(const Bases& b, const GemmGroup* groups, int ngroups, const GemmTerm* terms, int ntiles,
-                  double flops, double bytes) {
+void gemm_grouped(const Bases& b, const GemmGroup* groups, const int* tile_group, const GemmTerm* terms, int ntiles,
+                  bool split, double flops, double bytes) {
     if (ntiles <= 0) return;
-    launch(K_GEMM, flops, bytes, k_gemm_grouped, dim3(ntiles), dim3(256), 0, b, groups, ngroups, terms, ntiles);
+    if (split)
+        launch(K_GEMM, flops, bytes, k_gemm_grouped_split, dim3(ntiles), dim3(256), 0, b, groups, tile_group, terms);
+    else
+        launch(K_GEMM, flops, bytes, k_gemm_grouped, dim3((ntiles + 3) / 4), dim3(256), 0, b, groups, tile_group,
+               terms, ntiles);
     check(hipGetLastError(), "k_gemm_grouped");
 }
 void axpy_grouped(const Bases& b, const AxpyGroup* groups, int ngroups, const AxpyTerm* terms, double flops,
@@ -1354,17 +1434,19 @@ void to_f32(float* dst, const double* src, size_t n) {
     launch(K_VEC, 0.0, 12.0 * n, k_to_f32, dim3(nb), dim3(256), 0, dst, src, n);
     check(hipGetLastError(), "to_f32");
 }
-void gemm_grouped_lo(const BasesF& b, int mode, const GemmGroup* groups, int ngroups, const GemmTerm* terms,
-                     int ntiles, double flops, double bytes) {
+void gemm_grouped_lo(const BasesF& b, int mode, const GemmGroup* groups, const int* tile_group, const GemmTerm* terms,
+                     int ntiles, bool split, double flops, double bytes) {
     if (ntiles <= 0) return;
-    if (mode == 1)
-        launch(K_GEMM_LO, flops, bytes, k_gemm_grouped_lo<1>, dim3(ntiles), dim3(256), 0, b, groups, ngroups,
-               terms, ntiles);
-    else if (mode == 2)
-        launch(K_GEMM_LO, flops, bytes, k_gemm_grouped_lo<2>, dim3(ntiles), dim3(256), 0, b, groups, ngroups,
-               terms, ntiles);
+    if (mode != 1 && mode != 2) throw Error{MPSPT_E_ARG, "reduced-precision GEMM mode must be 1 (FP32) or 2 (BF16x3)"};
+    const dim3 grid(split ? ntiles : (ntiles + 3) / 4);
+    if (mode == 1 && split)
+        launch(K_GEMM_LO, flops, bytes, k_gemm_grouped_lo_split<1>, grid, dim3(256), 0, b, groups, tile_group, terms);
+    else if (mode == 1)
+        launch(K_GEMM_LO, flops, bytes, k_gemm_grouped_lo<1>, grid, dim3(256), 0, b, groups, tile_group, terms, ntiles);
+    else if (split)
+        launch(K_GEMM_LO, flops, bytes, k_gemm_grouped_lo_split<2>, grid, dim3(256), 0, b, groups, tile_group, terms);
     else
-        throw Error{MPSPT_E_ARG, "reduced-precision GEMM mode must be 1 (FP32) or 2 (BF16x3)"};
+        launch(K_GEMM_LO, flops, bytes, k_gemm_grouped_lo<2>, grid, dim3(256), 0, b, groups, tile_group, terms, ntiles);
     check(hipGetLastError(), "k_gemm_grouped_lo");
 }
 void axpy_grouped_lo(const BasesF& b, const AxpyGroup* groups, int ngroups, const AxpyTerm* terms, double flops,

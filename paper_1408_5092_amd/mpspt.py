@@ -262,17 +262,19 @@ class Context:
                                                 t.ctypes.data_as(C.POINTER(C.c_float)), C.byref(n)))
         return X, t
 
-    def profile(self, enable=True):
-        self._ok(self.lib.mpspt_profile(self.h, int(bool(enable))))
+    def profile(self, enable=True, every=1):
+        """Record kernel durations (every ``every``-th launch of each kind), or stop."""
+        self._ok(self.lib.mpspt_profile(self.h, int(every) if enable else 0))
 
     KERNELS = {0: "k_gemm_grouped", 1: "k_axpy_grouped", 2: "k_eig_reduce", 3: "k_diag_grouped", 4: "k_eig_vectors",
                5: "vector kernels", 6: "k_gemm_grouped_lo", 7: "k_axpy_grouped_lo"}
 
     def kernel_stats(self, kind):
-        s, n, f, b = C.c_double(), C.c_int64(), C.c_double(), C.c_double()
-        self._ok(self.lib.mpspt_kernel_stats(self.h, kind, C.byref(s), C.byref(n), C.byref(f), C.byref(b)))
+        s, n, f, b, na = C.c_double(), C.c_int64(), C.c_double(), C.c_double(), C.c_int64()
+        self._ok(self.lib.mpspt_kernel_stats(self.h, kind, C.byref(s), C.byref(n), C.byref(f), C.byref(b),
+                                             C.byref(na)))
         return dict(kernel=self.KERNELS.get(kind, str(kind)), seconds=s.value, launches=n.value, flops=f.value,
-                    bytes=b.value)
+                    bytes=b.value, launches_all=na.value)
 
     def get_trace(self):
         n = C.c_int32()

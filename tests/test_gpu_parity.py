@@ -206,3 +206,31 @@ def test_benchmark_workload_against_stored_oracle():
     assert res["e2"] >= gold["e2_exact"] - 1e-10
     for b, ob in enumerate(gold["bonds"]):
         assert ctx.get_bond(0, b) == [((n, s), d) for n, s, d in ob], f"bond {b}"
+
+
+def test_kernel_timing_sampling(mp, c1):
+    """Kernel timing records every launch, or a hashed one-in-N sample of each kind."""
+    ints, eri, psi0, ref = c1
+    print("case: 4a+4v M1=8 kernel timing every 1 / every 4", flush=True)
+    g = inputs.psi1_guess(4, 4, 4, 0, 8, 1000)
+    ctx = mp.Context(0)
+    ctx.load_integrals(4, 4, ints.h, ints.B)
+    ctx.load_h0_partition(ints.eps_virt)
+    ctx.load_psi0(4, 0, *psi0)
+    ctx.load_psi1_guess(g.bonds, g.sites)
+    for every in (1, 4):
+        ctx.profile(True, every=every)
+        ctx.sweep(8)
+        st = [ctx.kernel_stats(k) for k in sorted(ctx.KERNELS)]
+        ctx.profile(False)
+        gemm = st[0]
+        assert gemm["launches_all"] > 0 and gemm["seconds"] > 0
+        for s in st:
+            if every == 1:
+                assert s["launches"] == s["launches_all"], s
+            else:
+                assert s["launches"] <= s["launches_all"], s
+                if s["launches_all"] >= 400:
+                    assert abs(s["launches"] / s["launches_all"] - 1 / every) < 0.1, s
+    with pytest.raises(mp.MPSPTError):
+        ctx.profile(True, every=-1)
