@@ -44,18 +44,16 @@ PEAK_FP64_TFLOPS = 78.6
 
 
 def kernel_digest(name):
-    """sha256 of a kernel's source text in kernels.hip (signature through the closing brace)."""
+    """sha256 of the source section of kernels.hip that defines a kernel: the text between the
+    section rules ("// ----...") around its definition, so a change to any device function the
+    kernel uses from its section changes the digest."""
     import hashlib
     src = open(os.path.join(ROOT, "paper_1408_5092_amd", "csrc", "kernels.hip")).read()
     i = src.index(f"void {name}(")
-    i = src.rfind("\n", 0, i) + 1
-    k, depth = src.index("{", i), 0
-    while True:
-        depth += {"{": 1, "}": -1}.get(src[k], 0)
-        if depth == 0:
-            break
-        k += 1
-    return hashlib.sha256(src[i:k + 1].encode()).hexdigest()
+    rules = [m.start() for m in re.finditer(r"^// -{20,}", src, re.M)]
+    lo = max([r for r in rules if r < i], default=0)
+    hi = min([r for r in rules if r > i], default=len(src))
+    return hashlib.sha256(src[lo:hi].encode()).hexdigest()
 
 
 def measured_traffic(kernel):

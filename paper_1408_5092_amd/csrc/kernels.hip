@@ -1015,11 +1015,6 @@ struct Stream {
     // caching pool
     std::unordered_map<size_t, std::vector<void*>> free_blocks;
     std::unordered_map<void*, size_t> block_size;
-    // pinned staging ring for host-to-device copies, and a pinned bounce
-    // buffer for small device-to-host copies (both allocated on first use)
-    char* stage = nullptr;
-    size_t stage_head = 0;
-    char* bounce = nullptr;
     // profiling: every prof_every-th launch of each kind is recorded
     bool prof = false;
     int prof_every = 1;
@@ -1102,8 +1097,6 @@ void stream_destroy(Stream* s) {
         (void)hipEventDestroy(r.b);
     }
     for (hipEvent_t ev : s->event_pool) (void)hipEventDestroy(ev);
-    if (s->stage) (void)hipHostFree(s->stage);
-    if (s->bounce) (void)hipHostFree(s->bounce);
     // blocks still handed out (none once the engine is gone) stay with the runtime
     delete s;
     t_cur = prev == s ? nullptr : prev;
@@ -1162,53 +1155,15 @@ void trim() {
         }
     st.free_blocks.clear();
 }
-// Host-to-device copies go through a pinned ring: the source is copied into
-// the ring at once, and the DMA from the ring is ordered on the stream, so
-// the call never waits for earlier work (a pageable source would be staged
-// by the runtime, which can hold the host until the stream drains).  When
-// the ring wraps, the host waits for the stream once, so no region is
-// rewritten while a copy from it may still be pending.
-constexpr size_t kStageBytes = 32u << 20;
-constexpr size_t kBounceBytes = 1u << 20;
 void h2d(void* dst, const void* src, size_t bytes) {
     if (!bytes) return;
-    Stream& st = cur();
-    const size_t need = (bytes + 255) & ~size_t(255);
-    if (need > kStageBytes / 4) {  // large one-off inputs: the runtime stages them
-        check(hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, st.stream), "hipMemcpyAsync H2D");
-        return;
-    }
-    if (!st.stage) {
-        void* p = nullptr;
-        check(hipHostMalloc(&p, kStageBytes, hipHostMallocDefault), "hipHostMalloc");
-        st.stage = static_cast<char*>(p);
-        st.stage_head = 0;
-    }
-    if (st.stage_head + need > kStageBytes) {
-        check(hipStreamSynchronize(st.stream), "hipStreamSynchronize");
-        st.stage_head = 0;
-    }
-    char* slot = st.stage + st.stage_head;
-    std::memcpy(slot, src, bytes);
-    st.stage_head += need;
-    check(hipMemcpyAsync(dst, slot, bytes, hipMemcpyHostToDevice, st.stream), "hipMemcpyAsync H2D");
+    // ordered on the stream; pageable sources are staged by the runtime before it returns
+    check(hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, cur_stream()), "hipMemcpyAsync H2D");
 }
 void d2h(void* dst, const void* src, size_t bytes) {
     if (!bytes) return;
-    Stream& st = cur();
-    if (bytes <= kBounceBytes) {
-        if (!st.bounce) {
-            void* p = nullptr;
-            check(hipHostMalloc(&p, kBounceBytes, hipHostMallocDefault), "hipHostMalloc");
-            st.bounce = static_cast<char*>(p);
-        }
-        check(hipMemcpyAsync(st.bounce, src, bytes, hipMemcpyDeviceToHost, st.stream), "hipMemcpyAsync D2H");
-        check(hipStreamSynchronize(st.stream), "hipStreamSynchronize");
-        std::memcpy(dst, st.bounce, bytes);
-        return;
-    }
-    check(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, st.stream), "hipMemcpyAsync D2H");
-    check(hipStreamSynchronize(st.stream), "hipStreamSynchronize");
+    check(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, cur_stream()), "hipMemcpyAsync D2H");
+    check(hipStreamSynchronize(cur_stream()), "hipStreamSynchronize");
 }
 void d2d(void* dst, const void* src, size_t bytes) {
     if (!bytes) return;

@@ -12,8 +12,9 @@ the timed region.
       per-kernel average counter value (KiB) per dispatch in the window and
       the value of the largest plain copy (bench.py --copy-calibration),
       from DIR/*_counter_collection.csv (rocprofv3 --pmc COUNTER)
-  python -m paper_1408_5092_amd.profiling traffic FETCH_DIR WRITE_DIR KERNEL COPY_BYTES
-      HBM bytes per dispatch of KERNEL: each counter scaled by the ratio of
+  python -m paper_1408_5092_amd.profiling traffic FETCH_DIR WRITE_DIR KERNEL[,KERNEL...] COPY_BYTES
+      HBM bytes per dispatch of KERNEL (several names: their dispatches
+      together): each counter scaled by the ratio of
       the copy's true bytes (COPY_BYTES read, COPY_BYTES written) to what
       that counter reported for the copy
 
@@ -88,13 +89,22 @@ def counters(d, delete=False):
 
 
 def traffic(fetch_dir, write_dir, kernel, copy_bytes):
+    """KERNEL may list several comma-separated names (launch shapes of one kernel
+    kind); their per-dispatch averages are combined weighted by dispatches."""
     fs = json.load(open(os.path.join(fetch_dir, "counter_summary.json")))
     ws = json.load(open(os.path.join(write_dir, "counter_summary.json")))
     kib = copy_bytes / 1024.0
     f_scale, w_scale = kib / fs["copy_kib"], kib / ws["copy_kib"]
-    fk, wk = fs["kernels"][kernel]["avg_kib"], ws["kernels"][kernel]["avg_kib"]
-    return {"kernel": kernel, "fetch_kib": fk, "write_kib": wk, "fetch_scale": f_scale, "write_scale": w_scale,
-            "bytes_per_dispatch": 1024.0 * (fk * f_scale + wk * w_scale)}
+    names = kernel.split(",")
+
+    def avg(summary):
+        rows = [summary["kernels"][n] for n in names if n in summary["kernels"]]
+        n = sum(r["dispatches"] for r in rows)
+        return sum(r["avg_kib"] * r["dispatches"] for r in rows) / n if n else 0.0, n
+
+    (fk, nf), (wk, _) = avg(fs), avg(ws)
+    return {"kernel": kernel, "dispatches": nf, "fetch_kib": fk, "write_kib": wk, "fetch_scale": f_scale,
+            "write_scale": w_scale, "bytes_per_dispatch": 1024.0 * (fk * f_scale + wk * w_scale)}
 
 
 def main(argv):
