@@ -232,11 +232,14 @@ def keep_count(eigs, M, rel_floor=1e-14, gap=1e-4):
     sectors), drop those <= rel_floor * trace, and never cut inside a cluster
     of eigenvalues closer than a relative ``gap`` (so spin multiplets stay
     whole).  eigs: list of (lambda, sector, index).  Returns the kept prefix
-    length of the list sorted by (-lambda, sector, index)."""
+    length of the list sorted by (-lambda, sector, index).  A vanishing
+    density matrix (the local solution is exactly zero, which happens when
+    V|Psi0> has no component in the window's space) keeps min(M, dim) states
+    in (sector, index) order: every basis is then equally significant."""
     s = sorted(eigs, key=lambda t: (-t[0], t[1], t[2]))
     lam = np.array([t[0] for t in s])
     tr = lam.sum()
-    n_sig = int(np.sum(lam > rel_floor * tr)) if tr > 0 else 0
+    n_sig = int(np.sum(lam > rel_floor * tr)) if tr > 0 else len(lam)
     K0 = min(M, n_sig)
     K = K0
     while 0 < K < len(lam) and lam[K - 1] <= (1.0 + gap) * lam[K]:

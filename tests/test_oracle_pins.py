@@ -154,6 +154,14 @@ def test_zero_coupling_gives_zero():
     E0, c, ab = exact.active_ground_state(h, eri, ka, 4, 0)
     r = exact.brute_force(h, eri, ka, ints.eps_virt, 4, 0, c, ab)
     assert abs(r.E2) < 1e-14 and abs(r.E3) < 1e-14
+    # the sweep degenerates the same way: every local solution is zero, the
+    # truncation keeps min(M, dim) states of a vanishing density matrix, and
+    # the bonds stay within the admissible sectors
+    g = inputs.psi1_guess(ka, ints.k_v, 4, 0, 8, 1000)
+    sw = mps.Sweeper(h, eri, ka, ints.eps_virt, 4, 0, exact.psi0_mps(c, ab, ka), (g.bonds, g.sites), 8)
+    sw.run(n_sweeps=2)
+    assert all(t["e2"] == 0.0 for t in sw.trace) and sw.e3() == 0.0
+    assert all(sum(d for _, d in b) >= 1 for b in sw.bonds())
 
 
 # ------------------------------------------------------------------ MPO
