@@ -1281,7 +1281,9 @@ Sel select_states(const std::vector<std::vector<double>>& w, int M) {
         if (a.g != b.g) return a.g < b.g;
         return a.j < b.j;
     });
-    int nsig = 0;
+    // a vanishing density matrix (zero local solution) keeps min(M, dim)
+    // states in (sector, index) order: every basis is equally significant
+    int nsig = tr > 0 ? 0 : (int)all.size();
     if (tr > 0)
         for (auto& e : all) nsig += e.l > 1e-14 * tr;
     int K0 = std::min(M, nsig), K = K0;
@@ -1299,7 +1301,7 @@ Sel select_states(const std::vector<std::vector<double>>& w, int M) {
 }
 }  // namespace
 
-double Engine::truncate(int i, bool forward, const Two& lay, const double* x, int M, Site& C) {
+double Engine::truncate(int i, bool forward, const Two& lay, const double* x, int M, Site& C, bool zero) {
     // groups of rows (forward: (il, s1)) or columns (backward: (s2, jr)) by middle sector
     struct Part { int a, b, off, dim; };  // forward: a=il b=s1 ; backward: a=s2 b=jr
     std::map<QN, std::vector<Part>> groups;
@@ -1336,6 +1338,18 @@ double Engine::truncate(int i, bool forward, const Two& lay, const double* x, in
     std::vector<size_t> woff(ng);
     for (int g = 0; g < ng; ++g) { woff[g] = wsz; wsz += gdim[g]; }
     eigw_.ensure(std::max<size_t>(wsz, 1));
+    Sel sel;
+    if (zero) {
+        // x = 0: the density matrices vanish; keep identity bases (any
+        // orthonormal basis spans an equally insignificant kept space)
+        std::vector<std::vector<double>> w(ng);
+        for (int q = 0; q < ng; ++q) w[q].assign(gdim[q], 0.0);
+        sel = select_states(w, M);
+        std::vector<double> eye(std::max<size_t>(rsz, 1), 0.0);
+        for (int q = 0; q < ng; ++q)
+            for (int r = 0; r < gdim[q]; ++r) eye[goff[q] + (size_t)r * gdim[q] + r] = 1.0;
+        dev::h2d(rho_.p, eye.data(), rsz * sizeof(double));
+    } else {
     // reduced density matrices
     GemmBatch gr;
     int g = 0;
@@ -1399,7 +1413,7 @@ double Engine::truncate(int i, bool forward, const Two& lay, const double* x, in
     dev::d2h(wall.data(), eigw_.p, wsz * sizeof(double));
     std::vector<std::vector<double>> w(ng);
     for (int q = 0; q < ng; ++q) w[q].assign(wall.begin() + woff[q], wall.begin() + woff[q] + gdim[q]);
-    Sel sel = select_states(w, M);
+    sel = select_states(w, M);
     // orthonormal bases of the kept subspaces (first kept[q] columns of each
     // density matrix's buffer)
     {
@@ -1426,6 +1440,7 @@ double Engine::truncate(int i, bool forward, const Two& lay, const double* x, in
         dev::d2h(&bad, status, sizeof(int));
         if (bad) throw err(MPSPT_E_STATE, "eigensolver could not orthonormalise a kept basis");
     }
+    }  // !zero
     Bond nb;
     std::vector<int> gid;  // new sector -> group
     for (int q = 0; q < ng; ++q)
@@ -1585,6 +1600,7 @@ int Engine::solve(int i, double& e2) {
     }
     int it = 0;
     bool solved = false;
+    x_zero_ = false;
     // CG on A x = -b; convergence is confirmed on the true residual -b - A x
     // and CG restarts from x when the updated residual has drifted.
     const int max_restarts = lo ? 12 : 4;
@@ -1607,6 +1623,7 @@ int Engine::solve(int i, double& e2) {
         if (bb == 0.0) {
             dev::zero(x_.p, n * sizeof(double));
             dev::zero(q_.p, n * sizeof(double));
+            x_zero_ = true;
             solved = true;
             break;
         }
@@ -1765,7 +1782,7 @@ double Engine::run_sweeps(int M, int n_sweeps, int max_sweeps, double e_tol) {
                 last_lay_ = xlay_;
                 Site C;
                 double t = dev::now();
-                double disc = truncate(i, fwd, xlay_, x_.p, M, C);
+                double disc = truncate(i, fwd, xlay_, x_.p, M, C, !gs_ && x_zero_);
                 res_.t_phase[3] += dev::now() - t;
                 t = dev::now();
                 if (fwd) upd_left(i);

@@ -382,7 +382,9 @@ class Engine {
                      const double* xket, const Two& bra, double* ybra);
     void build_diag(int i, const Env& L, const Env& R, const TwoOp& O, const Two& lay, double* d, double shift);
     void contract_sites(const Site& A, const Site& B, const Two& lay, double* out);
-    double truncate(int i, bool forward, const Two& lay, const double* x, int M, Site& C);
+    // zero: x vanishes (the local right-hand side was zero); no eigensolve
+    double truncate(int i, bool forward, const Two& lay, const double* x, int M, Site& C, bool zero = false);
+    bool x_zero_ = false;  // the last local solve returned x = 0
     void next_guess(int i, bool forward, Site& C);
     int solve(int i, double& e2);
     int davidson(int i, double& e);

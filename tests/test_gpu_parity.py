@@ -234,3 +234,65 @@ def test_kernel_timing_sampling(mp, c1):
                     assert abs(s["launches"] / s["launches_all"] - 1 / every) < 0.1, s
     with pytest.raises(mp.MPSPTError):
         ctx.profile(True, every=-1)
+
+
+def test_degenerate_cases(mp, c1):
+    """Cases the method degenerates in, against the oracle's dense solve:
+    no coupling between active and virtual orbitals (V|Psi0> = 0, so E2 = E3 = 0
+    and every local right-hand side vanishes); a single virtual orbital; a
+    bond dimension of one (the most severe truncation: still an upper bound);
+    one electron."""
+    ints, eri, psi0, ref = c1
+    print("case: 4a+4v zero coupling", flush=True)
+    ka, k = 4, ints.k
+    nv = (np.arange(k) >= ka).astype(int)
+    cnt = nv[:, None, None, None] + nv[None, :, None, None] + nv[None, None, :, None] + nv[None, None, None, :]
+    eri0 = np.where((cnt == 1) | (cnt == 2), 0.0, eri)
+    h0 = ints.h.copy()
+    h0[:ka, ka:] = 0.0
+    h0[ka:, :ka] = 0.0
+    _, c, ab = exact.active_ground_state(h0, eri0, ka, 4, 0)
+    g = inputs.psi1_guess(4, 4, 4, 0, 16, 1000)
+    ctx = mp.Context(0)
+    ctx.load_integrals_eri(4, 4, h0, eri0)
+    ctx.load_h0_partition(ints.eps_virt)
+    ctx.load_psi0(4, 0, *exact.psi0_mps(c, ab, 4))
+    ctx.load_psi1_guess(g.bonds, g.sites)
+    r = ctx.sweep(16)
+    assert abs(r["e2"]) < 1e-14 and abs(r["e3"]) < 1e-14
+
+    print("case: 4a+1v exact, and M1=1 upper bound", flush=True)
+    ints1 = inputs.integrals(4, 1, 8, 6)
+    eri1 = fock.eri_from_cholesky(ints1.B)
+    _, c, ab = exact.active_ground_state(ints1.h, eri1, 4, 4, 0)
+    ex = exact.brute_force(ints1.h, eri1, 4, ints1.eps_virt, 4, 0, c, ab)
+    p0 = exact.psi0_mps(c, ab, 4)
+    for M1 in (64, 1):
+        g = inputs.psi1_guess(4, 1, 4, 0, M1, 1001)
+        ctx = mp.Context(0)
+        ctx.load_integrals(4, 1, ints1.h, ints1.B)
+        ctx.load_h0_partition(ints1.eps_virt)
+        ctx.load_psi0(4, 0, *p0)
+        ctx.load_psi1_guess(g.bonds, g.sites)
+        r = ctx.sweep(M1)
+        sw = mps.Sweeper(ints1.h, eri1, 4, ints1.eps_virt, 4, 0, p0, (g.bonds, g.sites), M1)
+        sw.run()
+        np.testing.assert_allclose(ctx.get_trace()["e2"], [t["e2"] for t in sw.trace], rtol=0, atol=1e-9)
+        if M1 == 64:
+            assert r["e2"] == pytest.approx(ex.E2, abs=1e-9) and r["e3"] == pytest.approx(ex.E3, abs=1e-9)
+        else:
+            assert r["e2"] >= ex.E2 - 1e-12
+
+    print("case: 3a+2v one electron", flush=True)
+    ints2 = inputs.integrals(3, 2, 6, 7)
+    eri2 = fock.eri_from_cholesky(ints2.B)
+    _, c, ab = exact.active_ground_state(ints2.h, eri2, 3, 1, 1)
+    ex = exact.brute_force(ints2.h, eri2, 3, ints2.eps_virt, 1, 1, c, ab)
+    g = inputs.random_mps(5, 3, 1, 1, (1, 2), 16, 1002)
+    ctx = mp.Context(0)
+    ctx.load_integrals(3, 2, ints2.h, ints2.B)
+    ctx.load_h0_partition(ints2.eps_virt)
+    ctx.load_psi0(1, 1, *exact.psi0_mps(c, ab, 3))
+    ctx.load_psi1_guess(g.bonds, g.sites)
+    r = ctx.sweep(16)
+    assert r["e2"] == pytest.approx(ex.E2, abs=1e-10) and r["e3"] == pytest.approx(ex.E3, abs=1e-10)
