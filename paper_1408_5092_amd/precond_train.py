@@ -1,6 +1,7 @@
 """Train the learned CG preconditioner on solves the method generates.
 
   python -m paper_1408_5092_amd.precond_train [--out FILE] [--steps N]
+  python -m paper_1408_5092_amd.precond_train --eval-pairs [--params FILE]
 
 Harvests (features, target) samples from Jacobi-preconditioned solves of
 the 4-active/4-virtual workload (seeds 0-31) and of the 8-active/16-virtual
@@ -9,6 +10,11 @@ kernels (mini-batch Adam), then compares CG iterations and solve time of
 Jacobi and learned preconditioning on held-out seeds (100-103 and 100-101).
 Psi0 comes from the library's DMRG, the Psi1 guess from the seeded input
 generator.  Everything runs through the C ABI.
+
+--eval-pairs evaluates a trained network (--params, default the file the
+training writes) on the virtual-pair form of the 12-active/40-virtual system
+instead: integral seeds 100-107, a seeded sample of pairs per seed, Jacobi
+against learned scaling on concurrent contexts, CG iterations and wall time.
 """
 import argparse
 import json
@@ -92,14 +98,67 @@ def evaluate(cases, params, log=print):
     return out
 
 
+PAIR_SHAPE = (12, 40, 12, 48, 256, 256)  # k_a, k_v, n_elec, Cholesky rank, M0, M1 per pair
+
+
+def evaluate_pairs(params, seeds=range(100, 108), n_pairs=8, contexts=8, log=print):
+    from . import pairs as pp
+    _torch_device()
+    k_a, k_v, n, rank, M0, M1 = PAIR_SHAPE
+    ctxs = pp.make_contexts(contexts)
+    rows = []
+    for seed in seeds:
+        ints = inputs.integrals(k_a, k_v, rank, seed)
+        c0 = mpspt.Context(0)
+        hp, Bp, ep = pp.pair_integrals(ints.h, ints.B, k_a, ints.eps_virt, 0, 0)
+        c0.load_integrals(k_a, 1, hp, Bp)
+        c0.load_h0_partition(ep)
+        g0 = inputs.psi0_guess(k_a, n, 0, M0, seed + 2000)
+        c0.ground_state(n, 0, g0.bonds, g0.sites, M0)
+        psi0 = ([c0.get_bond(1, i) for i in range(k_a + 1)], [c0.get_site(1, i) for i in range(k_a)])
+        c0.close()
+        allp = pp.pair_list(k_v)
+        rng = np.random.default_rng(seed)
+        sel = [allp[i] for i in sorted(rng.choice(len(allp), n_pairs, replace=False))]
+        guesses = {}
+        for (a, b) in sel:
+            mk = pp.pair_masks(a, b)
+            g = inputs.random_mps(k_a + len(mk), k_a, n, 0, (1, 2), M1, seed + 1000 + 100 * a + b, pp.mask_sets(mk))
+            guesses[(a, b)] = (g.bonds, g.sites)
+        row = {"case": f"pairs12a40v/{seed}", "pairs": [list(p) for p in sel]}
+        for label, pc in (("jacobi", 0), ("learned", 1)):
+            if pc:
+                for c in ctxs:
+                    c.precond_set(params)
+            e2, res, dt = pp.solve_pairs_concurrent(ctxs, ints.h, ints.B, k_a, ints.eps_virt, n, 0, psi0,
+                                                    lambda a, b: guesses[(a, b)], M1, pairs=sel, precond=pc)
+            row[label] = {"cg_iters": sum(r["cg_iters"] for r in res.values()), "seconds": dt, "e2": e2}
+        log(f"[eval] {row['case']}: CG iterations {row['jacobi']['cg_iters']} -> {row['learned']['cg_iters']}, "
+            f"time {row['jacobi']['seconds']:.2f}s -> {row['learned']['seconds']:.2f}s, "
+            f"dE2 {row['learned']['e2'] - row['jacobi']['e2']:.1e}")
+        rows.append(row)
+    for c in ctxs:
+        c.close()
+    return rows
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--out", default=os.path.join(os.path.dirname(__file__), "precond_params.npy"))
     ap.add_argument("--steps", type=int, default=400)
     ap.add_argument("--small-seeds", type=int, default=32)
     ap.add_argument("--large-seeds", type=int, default=4)
+    ap.add_argument("--eval-pairs", action="store_true", help="evaluate a trained network on the pair form")
+    ap.add_argument("--params", default=None, help="trained network (default: --out)")
+    ap.add_argument("--pairs-per-seed", type=int, default=8)
     args = ap.parse_args(argv)
     log = lambda m: print(m, flush=True)  # noqa: E731
+    if args.eval_pairs:
+        params = np.load(args.params or args.out)
+        rows = evaluate_pairs(params, n_pairs=args.pairs_per_seed, log=log)
+        tot = {k: sum(r[k]["cg_iters"] for r in rows) for k in ("jacobi", "learned")}
+        print(json.dumps({"eval_pairs": rows, "cg_iters_total": tot}))
+        return 0
     cases = [("4a4v", s) for s in range(args.small_seeds)] + [("8a16v", s) for s in range(args.large_seeds)]
     X, t = harvest(cases, log)
     log(f"[harvest] {len(t)} samples; target quantiles {np.quantile(t, [0.05, 0.5, 0.95])}")
