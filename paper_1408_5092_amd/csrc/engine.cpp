@@ -278,8 +278,15 @@ TwoOp make_twoop(const MPO& m, int i) {
 
 // ---------------------------------------------------------- work lists
 void SlotMap::ref(const double* p, int8_t& slot, int64_t& off) const {
+    // consecutive references usually fall in the same buffer; slots do not overlap
+    if (base_[last_] && p >= base_[last_] && p < base_[last_] + cnt_[last_]) {
+        slot = (int8_t)last_;
+        off = p - base_[last_];
+        return;
+    }
     for (int k = 0; k < dev::kAbsSlot; ++k)
         if (base_[k] && p >= base_[k] && p < base_[k] + cnt_[k]) {
+            last_ = k;
             slot = (int8_t)k;
             off = p - base_[k];
             return;
@@ -1139,6 +1146,11 @@ void Engine::build_effop(EffOp& op, const Env& L, const Env& R, const TwoOp& O, 
         op.st1.group(op.U.p + uoff[lb], ket.pw[B.ik], B.rows, ket.pw[B.ik], false);
         op.st1.term(L.data.p + B.off, B.cols, false, xket + ket.po[B.ik], ket.pw[B.ik], false, B.cols, 1.0);
         op.bytes += 8.0 * B.rows * B.cols;
+    }
+    {
+        size_t nt = 0;
+        for (const VB& v : vbs) nt += v.t.size();
+        op.st2.reserve(vbs.size(), nt);
     }
     for (const VB& v : vbs) {
         op.st2.group(op.V.p + v.off, v.cols, v.rows, v.cols, false);

@@ -134,6 +134,7 @@ class SlotMap {
   private:
     const double* base_[dev::kSlots] = {};
     size_t cnt_[dev::kSlots] = {};
+    mutable int last_ = 0;  // slot of the previous match, tried first
 };
 
 // Work list of grouped block axpys, reusable across launches.
@@ -146,6 +147,7 @@ class AxpyBatch {
     // slot-relative forms
     void group_ref(int8_t slot, int64_t off, int ldd, int m, int n, bool acc);
     void term_ref(int8_t slot, int64_t off, int lds, bool trans, double alpha);
+    void reserve(size_t groups, size_t terms) { g_.reserve(groups); t_.reserve(terms); }
     void upload();
     void run() const { run(slots_.bases()); }
     void run(const dev::Bases& b) const;
