@@ -180,7 +180,9 @@ __device__ inline void gemm_store(const typename GemmTypes<MODE>::B& bs, const G
 template <int MODE>
 __device__ inline void gemm_wave_per_tile(const typename GemmTypes<MODE>::B& bs, const GemmGroup* __restrict__ G,
                                           const int* __restrict__ TG, const GemmTerm* __restrict__ T, int ntiles) {
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    // the wave index is uniform across the wave: with it in a scalar register
+    // the tile's group and term records come through scalar loads
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
     const int tile = blockIdx.x * 4 + wave;
     if (tile >= ntiles) return;
     const GemmGroup g = G[TG[tile]];
