@@ -116,14 +116,15 @@ def make_contexts(n: int, device: int = 0):
 
 
 def solve_pairs_concurrent(contexts, h, B, k_a: int, eps_virt, n_elec: int, two_sz: int, psi0, guess_of,
-                           M1: int, pairs=None, **sweep_kw):
+                           M1: int, pairs=None, on_done=None, **sweep_kw):
     """Like ``solve_pairs``, with the pairs spread over one host thread per
     context.  Each context has its own stream, so one pair's host work (work
     lists, truncation bookkeeping, waits for convergence flags) overlaps the
     kernels of the others.  Pairs with two virtual sites are handed out
     first (they take longer).  Results do not depend on the number of
     contexts: every pair's sweep is the same sequence of launches on its
-    context's stream."""
+    context's stream.  on_done(pair, result, n_done), if given, is called as each
+    pair finishes (from the worker thread, under a lock)."""
     k_v = len(eps_virt)
     pairs = pair_list(k_v) if pairs is None else list(pairs)
     work = queue.Queue()
@@ -147,6 +148,8 @@ def solve_pairs_concurrent(contexts, h, B, k_a: int, eps_virt, n_elec: int, two_
                 return
             with lock:
                 out[(a, b)] = r
+                if on_done is not None:
+                    on_done((a, b), r, len(out))
 
     t0 = time.perf_counter()
     threads = [threading.Thread(target=worker, args=(c,)) for c in contexts]
@@ -212,9 +215,15 @@ def main(argv=None):
                               mask_sets(mk))
         gs[(x, y)] = (g.bonds, g.sites)
     ctxs = make_contexts(a.contexts)
+    t_start = time.perf_counter()
+
+    def progress(p, r, n):
+        if n % 50 == 0 or n == len(sel):
+            print(f"[pairs] {n}/{len(sel)} done ({time.perf_counter() - t_start:.1f}s)", flush=True)
+
     e2, res, dt = solve_pairs_concurrent(ctxs, ints.h, ints.B, a.k_a, ints.eps_virt, ne, 0, psi0,
-                                         lambda x, y: gs[(x, y)], a.m1, pairs=sel, n_sweeps=0, max_sweeps=12,
-                                         e_tol=a.e_tol, precision=a.precision)
+                                         lambda x, y: gs[(x, y)], a.m1, pairs=sel, on_done=progress, n_sweeps=0,
+                                         max_sweeps=12, e_tol=a.e_tol, precision=a.precision)
     print(json.dumps({
         "k_a": a.k_a, "k_v": a.k_v, "n_elec": ne, "rank": a.rank, "seed": a.seed, "M0": a.m0, "M1": a.m1,
         "precision": ["fp64", "fp32", "bf16x3"][a.precision], "contexts": a.contexts,
