@@ -189,3 +189,41 @@ def test_concurrent_contexts_match_sequential(mp, pp, large):
         assert r_con[p]["e2_sweep"] == r_seq[p]["e2_sweep"], p
         assert r_seq[p]["e2"] >= share[p] - 1e-10, p
     assert e_con == e_seq
+
+
+def test_pairs_at_the_12a40v_shape(mp, pp):
+    """The 12-active / 40-virtual pair problems (Psi0 by the library's DMRG at
+    M0 = 256), too large for the oracle's solves: properties that hold at any
+    size.  For three pairs (one diagonal): E2 < 0, the Hylleraas value does not
+    rise when M1 grows from 64 to 256 (both start from guesses at their own
+    bond dimension and are swept to convergence), and concurrent contexts give
+    the sequential energies bit for bit."""
+    k_a, k_v, ne, rank, M0 = 12, 40, 12, 48, 256
+    print("case: 12a+40v pairs (0,0) (3,17) (21,39) at M1 = 64 and 256", flush=True)
+    ints = inputs.integrals(k_a, k_v, rank, 0)
+    ctx = mp.Context(0)
+    hp, Bp, ep = pp.pair_integrals(ints.h, ints.B, k_a, ints.eps_virt, 0, 0)
+    ctx.load_integrals(k_a, 1, hp, Bp)
+    ctx.load_h0_partition(ep)
+    g0 = inputs.psi0_guess(k_a, ne, 0, M0, 2000)
+    ctx.ground_state(ne, 0, g0.bonds, g0.sites, M0)
+    psi0 = ([ctx.get_bond(1, i) for i in range(k_a + 1)], [ctx.get_site(1, i) for i in range(k_a)])
+    sample = [(0, 0), (3, 17), (21, 39)]
+    e2 = {}
+    for M1 in (64, 256):
+        def guess_of(a, b, M1=M1):
+            return guess(k_a, ne, a, b, M1, 1000 + 100 * a + b)
+        _, res, _ = pp.solve_pairs(ctx, ints.h, ints.B, k_a, ints.eps_virt, ne, 0, psi0, guess_of, M1,
+                                   pairs=sample)
+        for p, r in res.items():
+            assert r["flags"] == 0, p
+            e2[(p, M1)] = r["e2"]
+        if M1 == 256:
+            ctxs = pp.make_contexts(3)
+            _, rc, _ = pp.solve_pairs_concurrent(ctxs, ints.h, ints.B, k_a, ints.eps_virt, ne, 0, psi0, guess_of,
+                                                 M1, pairs=sample)
+            for p in sample:
+                assert rc[p]["e2"] == res[p]["e2"], p
+    for p in sample:
+        assert e2[(p, 256)] < 0.0
+        assert e2[(p, 256)] <= e2[(p, 64)] + 1e-10, p

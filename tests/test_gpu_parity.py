@@ -296,3 +296,16 @@ def test_degenerate_cases(mp, c1):
     ctx.load_psi1_guess(g.bonds, g.sites)
     r = ctx.sweep(16)
     assert r["e2"] == pytest.approx(ex.E2, abs=1e-10) and r["e3"] == pytest.approx(ex.E3, abs=1e-10)
+
+
+def test_size_limits(mp):
+    """Orbital counts beyond the library's limit (128) and empty spaces are refused."""
+    print("case: size limits", flush=True)
+    ctx = mp.Context(0)
+    for ka, kv in ((100, 29), (0, 4), (4, 0)):
+        k = ka + kv
+        h = np.eye(max(k, 1))[:k, :k]
+        B = np.zeros((1, k, k))
+        with pytest.raises(mp.MPSPTError) as e:
+            ctx.load_integrals(ka, kv, h, B)
+        assert e.value.status == -1  # MPSPT_E_ARG
