@@ -196,6 +196,20 @@ mpspt_status mpspt_mlp_train_step(mpspt_ctx *ctx, const float *X, const float *t
 mpspt_status mpspt_harvest(mpspt_ctx *ctx, int32_t enable);
 mpspt_status mpspt_harvest_get(mpspt_ctx *ctx, int64_t cap, float *X, float *t, int64_t *n_out);
 
+/* Launch-shape parameters of the grouped GEMM work lists of this context
+ * (they change how the same sums are tiled and split, not what is summed):
+ * wide_chunks (>= 1): a work list whose longest tile k chain has this many
+ * chunks of 16 runs one workgroup per 16 x 16 tile with the chunks spread
+ * over its four waves, else one wave per tile (default 8); kseg_min (>= 16)
+ * and kseg_div (>= 1): an output block whose summed k exceeds
+ * max(kseg_min, list work / kseg_div) is split into segments summed into the
+ * block in order (defaults 512 and 8192).  Work lists built afterwards use
+ * them; the values come from python -m paper_1408_5092_amd.autotune, which
+ * times candidates on a workload and records its choice in tuning.json.
+ * Errors: MPSPT_E_ARG for values out of range. */
+mpspt_status mpspt_set_tuning(mpspt_ctx *ctx, int32_t wide_chunks, int32_t kseg_min, int32_t kseg_div);
+mpspt_status mpspt_get_tuning(mpspt_ctx *ctx, int32_t *wide_chunks, int32_t *kseg_min, int32_t *kseg_div);
+
 /* Kernel timing: enable = N >= 1 starts recording the start and end of every
  * launch with probability 1/N, per kernel kind, on the context's stream with
  * HIP events (a fixed hash of the kind and the launch count decides, so the

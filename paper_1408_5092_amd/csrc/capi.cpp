@@ -259,6 +259,27 @@ mpspt_status mpspt_sweep(mpspt_ctx* ctx, const mpspt_sweep_params* params, mpspt
     });
 }
 
+mpspt_status mpspt_set_tuning(mpspt_ctx* ctx, int32_t wide_chunks, int32_t kseg_min, int32_t kseg_div) {
+    if (!ctx) return MPSPT_E_ARG;
+    return guard(ctx, [&] {
+        if (wide_chunks < 1 || kseg_min < 16 || kseg_div < 1) throw argerr("tuning values out of range");
+        mpspt::dev::Tuning& t = mpspt::dev::tuning();
+        t.wide_chunks = wide_chunks;
+        t.kseg_min = kseg_min;
+        t.kseg_div = kseg_div;
+    });
+}
+
+mpspt_status mpspt_get_tuning(mpspt_ctx* ctx, int32_t* wide_chunks, int32_t* kseg_min, int32_t* kseg_div) {
+    if (!ctx || !wide_chunks || !kseg_min || !kseg_div) return MPSPT_E_ARG;
+    return guard(ctx, [&] {
+        const mpspt::dev::Tuning& t = mpspt::dev::tuning();
+        *wide_chunks = t.wide_chunks;
+        *kseg_min = t.kseg_min;
+        *kseg_div = t.kseg_div;
+    });
+}
+
 mpspt_status mpspt_profile(mpspt_ctx* ctx, int32_t enable) {
     if (!ctx) return MPSPT_E_ARG;
     return guard(ctx, [&] {

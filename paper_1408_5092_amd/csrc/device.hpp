@@ -101,6 +101,15 @@ struct Stream;
 Stream* stream_create(int device, void* hip_stream);  // throws Error
 void stream_destroy(Stream* s);                        // waits for the stream, frees its pool
 void bind(Stream* s);                                  // make s current on this thread
+// Launch-shape parameters of the grouped GEMM work lists, per context:
+// wide_chunks: a list whose longest tile k chain has this many chunks of 16
+// runs one workgroup per tile with the chunks spread over its waves (else one
+// wave per tile); kseg_min / kseg_div: a group whose summed k exceeds
+// max(kseg_min, list work / kseg_div) is split into segments reduced in order.
+struct Tuning {
+    int wide_chunks = 8, kseg_min = 512, kseg_div = 8192;
+};
+Tuning& tuning();                                      // of the context bound to this thread
 int device_count();
 void* alloc(size_t bytes);                  // throws Error (MPSPT_E_NOMEM); stream-ordered pool
 void release(void* p);                      // back to the pool; safe while earlier launches run

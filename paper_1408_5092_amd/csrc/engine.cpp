@@ -342,10 +342,6 @@ void GemmBatch::term(const double* A, int lda, bool tA, const double* B, int ldb
 // into segments (at term boundaries, or inside a long term) that write
 // partial products to the batch's scratch; a grouped axpy then adds the
 // segments into C in order, so the result stays deterministic.
-// Launch shape: one workgroup per tile, k spread over its waves, once some
-// tile of the list has at least this many chunks of 16 in its k chain.
-constexpr long kWideChunks = 8;
-
 void GemmBatch::upload() {
     if (split_) {  // already laid out
         upload_lists();
@@ -365,7 +361,8 @@ void GemmBatch::upload() {
         live.push_back(g);
         ksum.push_back(K);
     }
-    const long kseg = std::max<long>(512, (long)(work / 8192.0));
+    const dev::Tuning& tu = dev::tuning();
+    const long kseg = std::max<long>(tu.kseg_min, (long)(work / (double)tu.kseg_div));
     size_t psz = 0;
     std::vector<int> nseg(live.size(), 1);
     for (size_t gi = 0; gi < live.size(); ++gi)
@@ -451,7 +448,9 @@ void GemmBatch::upload_lists() {
         for (int t = 0; t < g.nterms; ++t) kc += (t_[g.term0 + t].k + 15) / 16;
         maxc = std::max(maxc, kc);
     }
-    wide_ = maxc >= kWideChunks;
+    // launch shape: one workgroup per tile, k spread over its waves, once some
+    // tile of the list has a long enough k chain
+    wide_ = maxc >= dev::tuning().wide_chunks;
     dg_.upload(g_);
     dt_.upload(t_);
     dtg_.upload(tg);

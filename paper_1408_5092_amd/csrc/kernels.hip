@@ -1014,6 +1014,7 @@ struct ProfRec {
 struct Stream {
     int device = 0;
     hipStream_t stream = nullptr;
+    Tuning tune;
     // caching pool
     std::unordered_map<size_t, std::vector<void*>> free_blocks;
     std::unordered_map<void*, size_t> block_size;
@@ -1062,6 +1063,8 @@ void setup_device(int device) {
     g_setup_done[device] = true;
 }
 }  // namespace
+
+Tuning& tuning() { return cur().tune; }
 
 Stream* stream_create(int device, void* hip_stream) {
     int n = 0;

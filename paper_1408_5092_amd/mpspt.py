@@ -7,19 +7,22 @@ library is PyTorch's current HIP stream when torch is importable.
 from __future__ import annotations
 
 import ctypes as C
+import json
 import os
 
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libmpspt.so")
+# launch-shape choice recorded by python -m paper_1408_5092_amd.autotune
+TUNING_PATH = os.path.join(_HERE, "tuning.json")
 
 STATUS = {0: "MPSPT_OK", -1: "MPSPT_E_ARG", -2: "MPSPT_E_QN", -3: "MPSPT_E_NOMEM", -4: "MPSPT_E_HIP",
           -5: "MPSPT_E_INDEFINITE", -6: "MPSPT_E_STATE", -7: "MPSPT_E_NODEV"}
 
 EXPORTED = ["mpspt_create", "mpspt_destroy", "mpspt_last_error", "mpspt_load_integrals",
             "mpspt_load_integrals_eri", "mpspt_load_h0_partition", "mpspt_load_psi0",
-            "mpspt_restrict_virtual", "mpspt_load_psi1_guess", "mpspt_ground_state", "mpspt_sweep", "mpspt_profile",
+            "mpspt_restrict_virtual", "mpspt_load_psi1_guess", "mpspt_ground_state", "mpspt_sweep", "mpspt_profile", "mpspt_set_tuning", "mpspt_get_tuning",
             "mpspt_kernel_stats", "mpspt_get_trace", "mpspt_get_bond",
             "mpspt_get_site", "mpspt_mpo_dense", "mpspt_mpo_dims", "mpspt_precond_set", "mpspt_precond_get",
             "mpspt_mlp_grad", "mpspt_mlp_train_step", "mpspt_harvest", "mpspt_harvest_get"]
@@ -146,6 +149,10 @@ class Context:
         if st != 0:
             raise MPSPTError(st, self.lib.mpspt_last_error(None).decode())
         self.h = h
+        if os.path.exists(TUNING_PATH):
+            with open(TUNING_PATH) as f:
+                t = json.load(f)["choice"]
+            self.set_tuning(t["wide_chunks"], t["kseg_min"], t["kseg_div"])
 
     def close(self):
         if getattr(self, "h", None):
@@ -261,6 +268,14 @@ class Context:
             self._ok(self.lib.mpspt_harvest_get(self.h, n.value, X.ctypes.data_as(C.POINTER(C.c_float)),
                                                 t.ctypes.data_as(C.POINTER(C.c_float)), C.byref(n)))
         return X, t
+
+    def set_tuning(self, wide_chunks, kseg_min, kseg_div):
+        self._ok(self.lib.mpspt_set_tuning(self.h, int(wide_chunks), int(kseg_min), int(kseg_div)))
+
+    def get_tuning(self):
+        a, b, c = C.c_int32(), C.c_int32(), C.c_int32()
+        self._ok(self.lib.mpspt_get_tuning(self.h, C.byref(a), C.byref(b), C.byref(c)))
+        return {"wide_chunks": a.value, "kseg_min": b.value, "kseg_div": c.value}
 
     def profile(self, enable=True, every=1):
         """Record kernel durations (every ``every``-th launch of each kind), or stop."""
