@@ -661,6 +661,21 @@ void Engine::ensure_partials() {
 Engine::~Engine() {
     dev::host_free(hsc_);
     for (void* e : ev_) dev::event_destroy(e);
+    dev::host_free(eig_status_h_);
+    dev::event_destroy(eig_ev_);
+}
+
+void Engine::drop_eig_status() {  // a flag left by an earlier call that stopped on an error
+    if (!eig_pending_) return;
+    dev::event_wait(eig_ev_);
+    eig_pending_ = false;
+}
+
+void Engine::check_eig_status() {
+    if (!eig_pending_) return;
+    dev::event_wait(eig_ev_);
+    eig_pending_ = false;
+    if (*eig_status_h_) throw err(MPSPT_E_STATE, "eigensolver could not orthonormalise a kept basis");
 }
 
 void Engine::clear_plans() {
@@ -1441,15 +1456,20 @@ double Engine::truncate(int i, bool forward, const Two& lay, const double* x, in
         }
         eigS_.ensure(1);
         int* status = reinterpret_cast<int*>(eigS_.p);
+        check_eig_status();  // the previous window's flag, before it is reset
         dev::zero(status, sizeof(int));
         DevArr<dev::EigJob> dj[2];
         for (int c = 0; c < 2; ++c) {
             dj[c].upload(jobs[c]);
             if (!jobs[c].empty()) dev::eig_vectors(dj[c].p, (int)jobs[c].size(), nmax[c], kmax[c], status);
         }
-        int bad = 0;
-        dev::d2h(&bad, status, sizeof(int));
-        if (bad) throw err(MPSPT_E_STATE, "eigensolver could not orthonormalise a kept basis");
+        if (!eig_status_h_) {
+            eig_status_h_ = static_cast<int*>(dev::host_alloc(sizeof(int)));
+            eig_ev_ = dev::event_create();
+        }
+        dev::d2h_async(eig_status_h_, status, sizeof(int));
+        dev::event_record(eig_ev_);
+        eig_pending_ = true;
     }
     }  // !zero
     Bond nb;
@@ -1819,12 +1839,14 @@ double Engine::run_sweeps(int M, int n_sweeps, int max_sweeps, double e_tol) {
             if (res_.n_sweeps >= max_sweeps) break;
         }
     }
+    check_eig_status();
     return e2;
 }
 
 SweepResult Engine::sweep(const SweepParams& p) {
     if (!have_psi1) throw err(MPSPT_E_STATE, "load integrals, the H0 partition, Psi0 and a Psi1 guess first");
     if (p.M1 < 1) throw err(MPSPT_E_ARG, "M1 must be positive");
+    drop_eig_status();
     res_ = SweepResult();
     res_.e0 = E0_;
     trace_.clear();
@@ -1855,6 +1877,7 @@ SweepResult Engine::sweep(const SweepParams& p) {
 
 double Engine::ground_state(int n_elec, int two_sz, const std::vector<Bond>& bonds,
                             const std::vector<std::vector<double>>& sites, int M0, int n_sweeps, double e_tol) {
+    drop_eig_status();
     if (!have_part) throw err(MPSPT_E_STATE, "load integrals and the H0 partition before the ground-state sweep");
     if ((int)bonds.size() != k_a_ + 1 || (int)sites.size() != k_a_) throw err(MPSPT_E_ARG, "guess needs k_a sites");
     if (k_a_ < 2) throw err(MPSPT_E_ARG, "the ground-state sweep needs at least two active orbitals");

@@ -366,6 +366,14 @@ class Engine {
     void precond_apply(int i, int nb);
     void harvest_window(int i, int nb);
     double* hsc_ = nullptr;  // pinned host copies of the CG scalars, two slots
+    // The eigensolver's failure flag is read back without waiting: a pinned
+    // copy and an event, checked before the flag is reused and at the end of
+    // the sweeps, so the host builds the next tensors while the kernel runs.
+    int* eig_status_h_ = nullptr;
+    void* eig_ev_ = nullptr;
+    bool eig_pending_ = false;
+    void check_eig_status();
+    void drop_eig_status();
     void* ev_[2] = {nullptr, nullptr};
     EffOp& effop(int r, int i, const Env& L, const Env& R, const TwoOp& O, const Two& ket, const double* xket,
                  const Two& bra, double* ybra);
