@@ -659,6 +659,12 @@ void Engine::ensure_partials() {
 }
 
 Engine::~Engine() {
+    // copies into the pinned buffers below may still be in flight (a sweep
+    // that stopped on an error leaves them): drain the stream first
+    try {
+        dev::sync();
+    } catch (...) {
+    }
     dev::host_free(hsc_);
     for (void* e : ev_) dev::event_destroy(e);
     dev::host_free(eig_status_h_);
