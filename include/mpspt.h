@@ -199,16 +199,19 @@ mpspt_status mpspt_harvest_get(mpspt_ctx *ctx, int64_t cap, float *X, float *t, 
 /* Launch-shape parameters of the grouped GEMM work lists of this context
  * (they change how the same sums are tiled and split, not what is summed):
  * wide_chunks (>= 1): a work list whose longest tile k chain has this many
- * chunks of 16 runs one workgroup per 16 x 16 tile with the chunks spread
- * over its four waves, else one wave per tile (default 8); kseg_min (>= 16)
+ * chunks of 16 runs one workgroup of split_waves (4, 8 or 16; default 4)
+ * waves per 16 x 16 tile with the chunks spread over them, else one wave
+ * per tile (default 8); kseg_min (>= 16)
  * and kseg_div (>= 1): an output block whose summed k exceeds
  * max(kseg_min, list work / kseg_div) is split into segments summed into the
  * block in order (defaults 512 and 8192).  Work lists built afterwards use
  * them; the values come from python -m paper_1408_5092_amd.autotune, which
  * times candidates on a workload and records its choice in tuning.json.
  * Errors: MPSPT_E_ARG for values out of range. */
-mpspt_status mpspt_set_tuning(mpspt_ctx *ctx, int32_t wide_chunks, int32_t kseg_min, int32_t kseg_div);
-mpspt_status mpspt_get_tuning(mpspt_ctx *ctx, int32_t *wide_chunks, int32_t *kseg_min, int32_t *kseg_div);
+mpspt_status mpspt_set_tuning(mpspt_ctx *ctx, int32_t wide_chunks, int32_t kseg_min, int32_t kseg_div,
+                              int32_t split_waves);
+mpspt_status mpspt_get_tuning(mpspt_ctx *ctx, int32_t *wide_chunks, int32_t *kseg_min, int32_t *kseg_div,
+                              int32_t *split_waves);
 
 /* Kernel timing: enable = N >= 1 starts recording the start and end of every
  * launch with probability 1/N, per kernel kind, on the context's stream with

@@ -2,10 +2,10 @@
 
     python -m paper_1408_5092_amd.autotune [--write]
 
-The grouped GEMM sums the same terms whichever way a work list is tiled; two
+The grouped GEMM sums the same terms whichever way a work list is tiled; four
 parameters choose how (see mpspt_set_tuning): the k-chain length at which a
-list runs one workgroup per 16 x 16 tile with its k chunks spread over four
-waves instead of one wave per tile (wide_chunks), and the segment length
+list runs one workgroup per 16 x 16 tile with its k chunks spread over 4, 8
+or 16 waves (split_waves) instead of one wave per tile (wide_chunks), and the segment length
 above which an output block's k range is split and reduced in order
 (kseg_min, kseg_div).  This script runs the 8-active / 16-virtual benchmark
 solve (Psi0 by the library's DMRG at M0 = 64, M1 = 128, Jacobi PCG, four
@@ -26,12 +26,13 @@ import time
 
 from . import inputs, mpspt
 
-DEFAULT = {"wide_chunks": 8, "kseg_min": 512, "kseg_div": 8192}
-GRID = {"wide_chunks": (4, 8, 16, 1 << 20), "kseg_min": (256, 512, 1024), "kseg_div": (4096, 8192, 16384)}
+DEFAULT = {"wide_chunks": 8, "kseg_min": 512, "kseg_div": 8192, "split_waves": 4}
+GRID = {"wide_chunks": (2, 4, 8, 1 << 20), "kseg_min": (128, 256, 512), "kseg_div": (8192, 16384),
+        "split_waves": (4, 8, 16)}
 
 
 def measure(ctx, M1, sweeps, tune):
-    ctx.set_tuning(tune["wide_chunks"], tune["kseg_min"], tune["kseg_div"])
+    ctx.set_tuning(tune["wide_chunks"], tune["kseg_min"], tune["kseg_div"], tune["split_waves"])
     ctx.profile(True, every=1)
     t = time.perf_counter()
     r = ctx.sweep(M1, n_sweeps=sweeps, compute_e3=False)

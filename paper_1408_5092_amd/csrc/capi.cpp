@@ -259,24 +259,29 @@ mpspt_status mpspt_sweep(mpspt_ctx* ctx, const mpspt_sweep_params* params, mpspt
     });
 }
 
-mpspt_status mpspt_set_tuning(mpspt_ctx* ctx, int32_t wide_chunks, int32_t kseg_min, int32_t kseg_div) {
+mpspt_status mpspt_set_tuning(mpspt_ctx* ctx, int32_t wide_chunks, int32_t kseg_min, int32_t kseg_div,
+                              int32_t split_waves) {
     if (!ctx) return MPSPT_E_ARG;
     return guard(ctx, [&] {
         if (wide_chunks < 1 || kseg_min < 16 || kseg_div < 1) throw argerr("tuning values out of range");
+        if (split_waves != 4 && split_waves != 8 && split_waves != 16) throw argerr("split_waves must be 4, 8 or 16");
         mpspt::dev::Tuning& t = mpspt::dev::tuning();
         t.wide_chunks = wide_chunks;
         t.kseg_min = kseg_min;
         t.kseg_div = kseg_div;
+        t.split_waves = split_waves;
     });
 }
 
-mpspt_status mpspt_get_tuning(mpspt_ctx* ctx, int32_t* wide_chunks, int32_t* kseg_min, int32_t* kseg_div) {
-    if (!ctx || !wide_chunks || !kseg_min || !kseg_div) return MPSPT_E_ARG;
+mpspt_status mpspt_get_tuning(mpspt_ctx* ctx, int32_t* wide_chunks, int32_t* kseg_min, int32_t* kseg_div,
+                              int32_t* split_waves) {
+    if (!ctx || !wide_chunks || !kseg_min || !kseg_div || !split_waves) return MPSPT_E_ARG;
     return guard(ctx, [&] {
         const mpspt::dev::Tuning& t = mpspt::dev::tuning();
         *wide_chunks = t.wide_chunks;
         *kseg_min = t.kseg_min;
         *kseg_div = t.kseg_div;
+        *split_waves = t.split_waves;
     });
 }
 

@@ -103,11 +103,12 @@ void stream_destroy(Stream* s);                        // waits for the stream, 
 void bind(Stream* s);                                  // make s current on this thread
 // Launch-shape parameters of the grouped GEMM work lists, per context:
 // wide_chunks: a list whose longest tile k chain has this many chunks of 16
-// runs one workgroup per tile with the chunks spread over its waves (else one
-// wave per tile); kseg_min / kseg_div: a group whose summed k exceeds
-// max(kseg_min, list work / kseg_div) is split into segments reduced in order.
+// runs one workgroup of split_waves (4, 8 or 16) waves per tile with the
+// chunks spread over them (else one wave per tile); kseg_min / kseg_div: a
+// group whose summed k exceeds max(kseg_min, list work / kseg_div) is split
+// into segments reduced in order.
 struct Tuning {
-    int wide_chunks = 8, kseg_min = 512, kseg_div = 8192;
+    int wide_chunks = 8, kseg_min = 512, kseg_div = 8192, split_waves = 4;
 };
 Tuning& tuning();                                      // of the context bound to this thread
 int device_count();
@@ -131,11 +132,11 @@ void event_wait(void* e);
 double now();  // host seconds
 
 // flops / bytes: algorithmic work of the launch, used only by the profiler
-// tile_group[t]: the group of tile t.  split: one workgroup per tile with the
-// tile's k chunks spread over its four waves (long k chains), else one wave
-// per tile.
+// tile_group[t]: the group of tile t.  waves = 4, 8 or 16: one workgroup of
+// that many waves per tile with the tile's k chunks spread over them (long k
+// chains); 0: one wave per tile.
 void gemm_grouped(const Bases& b, const GemmGroup* groups, const int* tile_group, const GemmTerm* terms, int ntiles,
-                  bool split, double flops = 0, double bytes = 0);
+                  int waves, double flops = 0, double bytes = 0);
 void axpy_grouped(const Bases& b, const AxpyGroup* groups, int ngroups, const AxpyTerm* terms, double flops = 0,
                   double bytes = 0);
 
@@ -186,7 +187,7 @@ void axpby(double* y, const double* x, double a, double b, size_t n);
 // Reduced-precision sigma (mode 1: FP32 MFMA, 2: BF16x3 split products with
 // FP32 accumulation) over the same work lists, on FP32 operand copies.
 void gemm_grouped_lo(const BasesF& b, int mode, const GemmGroup* groups, const int* tile_group, const GemmTerm* terms,
-                     int ntiles, bool split, double flops = 0, double bytes = 0);
+                     int ntiles, int waves, double flops = 0, double bytes = 0);
 void axpy_grouped_lo(const BasesF& b, const AxpyGroup* groups, int ngroups, const AxpyTerm* terms, double flops = 0,
                      double bytes = 0);
 void to_f32(float* dst, const double* src, size_t n);

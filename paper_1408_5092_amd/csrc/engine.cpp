@@ -450,7 +450,7 @@ void GemmBatch::upload_lists() {
     }
     // launch shape: one workgroup per tile, k spread over its waves, once some
     // tile of the list has a long enough k chain
-    wide_ = maxc >= dev::tuning().wide_chunks;
+    waves_ = maxc >= dev::tuning().wide_chunks ? dev::tuning().split_waves : 0;
     dg_.upload(g_);
     dt_.upload(t_);
     dtg_.upload(tg);
@@ -459,14 +459,14 @@ void GemmBatch::upload_lists() {
 void GemmBatch::run() const {
     dev::Bases b = slots_.bases();
     b.p[kPartSlot] = part_.p;
-    if (tiles_ > 0) dev::gemm_grouped(b, dg_.p, dtg_.p, dt_.p, tiles_, wide_, flops_, bytes_);
+    if (tiles_ > 0) dev::gemm_grouped(b, dg_.p, dtg_.p, dt_.p, tiles_, waves_, flops_, bytes_);
     red_.run(b);
 }
 void GemmBatch::run_lo(const dev::BasesF& b, int mode) const {
     if (abs_) throw err(MPSPT_E_STATE, "reduced-precision work list refers outside its bound buffers");
     dev::BasesF c = b;
     c.p[kPartSlot] = reinterpret_cast<float*>(part_.p);
-    if (tiles_ > 0) dev::gemm_grouped_lo(c, mode, dg_.p, dtg_.p, dt_.p, tiles_, wide_, flops_, bytes_ / 2);
+    if (tiles_ > 0) dev::gemm_grouped_lo(c, mode, dg_.p, dtg_.p, dt_.p, tiles_, waves_, flops_, bytes_ / 2);
     red_.run_lo(c);
 }
 

@@ -192,7 +192,7 @@ class GemmBatch {
     DevArr<dev::GemmGroup> dg_;
     DevArr<dev::GemmTerm> dt_;
     DevArr<int> dtg_;    // tile -> group
-    bool wide_ = false;  // launch shape: one workgroup per tile (long k chains)
+    int waves_ = 0;  // launch shape: waves per tile's workgroup (long k chains), 0: one wave per tile
     int tiles_ = 0;
     double flops_ = 0, bytes_ = 0;
     void upload_lists();

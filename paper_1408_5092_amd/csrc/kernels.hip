@@ -51,10 +51,11 @@ typedef double d4 __attribute__((ext_vector_type(4)));
 // range cut into chunks of 16.  Two launch shapes over the same lists:
 //   k_gemm_grouped:       one wave per tile (four tiles per workgroup), for
 //                         lists whose tiles have short k chains;
-//   k_gemm_grouped_split: one workgroup per tile, the chunks dealt
-//                         round-robin to the four waves (chunk c to wave
-//                         c % 4) and the partial tiles added in wave order
-//                         through LDS, for lists with long k chains.
+//   k_gemm_grouped_split: one workgroup of W = 4, 8 or 16 waves per tile,
+//                         the chunks dealt round-robin to the waves (chunk
+//                         c to wave c % W) and the partial tiles added in
+//                         wave order through LDS, for lists with long k
+//                         chains.
 // No LDS staging of operands: each lane loads its MFMA operands straight from
 // global memory, two chunks in flight; rows, columns and k beyond the block
 // load as zeros.  Results are deterministic for either shape.
@@ -193,7 +194,7 @@ __device__ inline void gemm_wave_per_tile(const typename GemmTypes<MODE>::B& bs,
     gemm_store<MODE>(bs, g, row0, col0, lane, acc);
 }
 
-template <int MODE>
+template <int MODE, int W>
 __device__ inline void gemm_split_tile(const typename GemmTypes<MODE>::B& bs, const GemmGroup* __restrict__ G,
                                        const int* __restrict__ TG, const GemmTerm* __restrict__ T,
                                        typename GemmTypes<MODE>::V (*part)[64]) {
@@ -203,12 +204,12 @@ __device__ inline void gemm_split_tile(const typename GemmTypes<MODE>::B& bs, co
     const int tiles_n = (g.n + GEMM_TILE - 1) / GEMM_TILE;
     const int t = tile - g.tile0;
     const int row0 = (t / tiles_n) * GEMM_TILE, col0 = (t % tiles_n) * GEMM_TILE;
-    auto acc = gemm_tile<MODE>(bs, g, T, row0, col0, lane, wave, 4);
+    auto acc = gemm_tile<MODE>(bs, g, T, row0, col0, lane, wave, W);
     if (wave > 0) part[wave - 1][lane] = acc;
     __syncthreads();
     if (wave != 0) return;
 #pragma unroll
-    for (int w = 0; w < 3; ++w) acc += part[w][lane];
+    for (int w = 0; w < W - 1; ++w) acc += part[w][lane];
     gemm_store<MODE>(bs, g, row0, col0, lane, acc);
 }
 
@@ -218,11 +219,12 @@ __global__ __launch_bounds__(256) void k_gemm_grouped(Bases bs, const GemmGroup*
     gemm_wave_per_tile<0>(bs, G, TG, T, ntiles);
 }
 
-__global__ __launch_bounds__(256) void k_gemm_grouped_split(Bases bs, const GemmGroup* __restrict__ G,
-                                                            const int* __restrict__ TG,
-                                                            const GemmTerm* __restrict__ T) {
-    __shared__ d4 part[3][64];
-    gemm_split_tile<0>(bs, G, TG, T, part);
+template <int W>
+__global__ __launch_bounds__(64 * W) void k_gemm_grouped_split(Bases bs, const GemmGroup* __restrict__ G,
+                                                              const int* __restrict__ TG,
+                                                              const GemmTerm* __restrict__ T) {
+    __shared__ d4 part[W - 1][64];
+    gemm_split_tile<0, W>(bs, G, TG, T, part);
 }
 
 template <int MODE>
@@ -232,12 +234,12 @@ __global__ __launch_bounds__(256) void k_gemm_grouped_lo(BasesF bs, const GemmGr
     gemm_wave_per_tile<MODE>(bs, G, TG, T, ntiles);
 }
 
-template <int MODE>
-__global__ __launch_bounds__(256) void k_gemm_grouped_lo_split(BasesF bs, const GemmGroup* __restrict__ G,
-                                                               const int* __restrict__ TG,
-                                                               const GemmTerm* __restrict__ T) {
-    __shared__ f4 part[3][64];
-    gemm_split_tile<MODE>(bs, G, TG, T, part);
+template <int MODE, int W>
+__global__ __launch_bounds__(64 * W) void k_gemm_grouped_lo_split(BasesF bs, const GemmGroup* __restrict__ G,
+                                                                 const int* __restrict__ TG,
+                                                                 const GemmTerm* __restrict__ T) {
+    __shared__ f4 part[W - 1][64];
+    gemm_split_tile<MODE, W>(bs, G, TG, T, part);
 }
 
 // ------------------------------------------------------------------- AXPY
@@ -1291,11 +1293,22 @@ KernelStats profile_stats(int kind) {
 }
 
 void gemm_grouped(const Bases& b, const GemmGroup* groups, const int* tile_group, const GemmTerm* terms, int ntiles,
-                  bool split, double flops, double bytes) {
+                  int waves, double flops, double bytes) {
     if (ntiles <= 0) return;
-    if (split)
-        launch(K_GEMM, flops, bytes, k_gemm_grouped_split, dim3(ntiles), dim3(256), 0, b, groups, tile_group, terms);
-    else
+    if (waves != 0 && waves != 4 && waves != 8 && waves != 16)
+        throw Error{MPSPT_E_ARG, "grouped GEMM: waves per tile must be 0, 4, 8 or 16"};
+    if (waves) {
+        const int w = waves;
+        if (w == 16)
+            launch(K_GEMM, flops, bytes, k_gemm_grouped_split<16>, dim3(ntiles), dim3(1024), 0, b, groups, tile_group,
+                   terms);
+        else if (w == 8)
+            launch(K_GEMM, flops, bytes, k_gemm_grouped_split<8>, dim3(ntiles), dim3(512), 0, b, groups, tile_group,
+                   terms);
+        else
+            launch(K_GEMM, flops, bytes, k_gemm_grouped_split<4>, dim3(ntiles), dim3(256), 0, b, groups, tile_group,
+                   terms);
+    } else
         launch(K_GEMM, flops, bytes, k_gemm_grouped, dim3((ntiles + 3) / 4), dim3(256), 0, b, groups, tile_group,
                terms, ntiles);
     check(hipGetLastError(), "k_gemm_grouped");
@@ -1394,19 +1407,32 @@ void to_f32(float* dst, const double* src, size_t n) {
     launch(K_VEC, 0.0, 12.0 * n, k_to_f32, dim3(nb), dim3(256), 0, dst, src, n);
     check(hipGetLastError(), "to_f32");
 }
+template <int MODE>
+static void gemm_lo_launch(const BasesF& b, const GemmGroup* groups, const int* tile_group, const GemmTerm* terms,
+                           int ntiles, int waves, double flops, double bytes) {
+    if (waves == 16)
+        launch(K_GEMM_LO, flops, bytes, k_gemm_grouped_lo_split<MODE, 16>, dim3(ntiles), dim3(1024), 0, b, groups,
+               tile_group, terms);
+    else if (waves == 8)
+        launch(K_GEMM_LO, flops, bytes, k_gemm_grouped_lo_split<MODE, 8>, dim3(ntiles), dim3(512), 0, b, groups,
+               tile_group, terms);
+    else if (waves == 4)
+        launch(K_GEMM_LO, flops, bytes, k_gemm_grouped_lo_split<MODE, 4>, dim3(ntiles), dim3(256), 0, b, groups,
+               tile_group, terms);
+    else
+        launch(K_GEMM_LO, flops, bytes, k_gemm_grouped_lo<MODE>, dim3((ntiles + 3) / 4), dim3(256), 0, b, groups,
+               tile_group, terms, ntiles);
+}
 void gemm_grouped_lo(const BasesF& b, int mode, const GemmGroup* groups, const int* tile_group, const GemmTerm* terms,
-                     int ntiles, bool split, double flops, double bytes) {
+                     int ntiles, int waves, double flops, double bytes) {
     if (ntiles <= 0) return;
     if (mode != 1 && mode != 2) throw Error{MPSPT_E_ARG, "reduced-precision GEMM mode must be 1 (FP32) or 2 (BF16x3)"};
-    const dim3 grid(split ? ntiles : (ntiles + 3) / 4);
-    if (mode == 1 && split)
-        launch(K_GEMM_LO, flops, bytes, k_gemm_grouped_lo_split<1>, grid, dim3(256), 0, b, groups, tile_group, terms);
-    else if (mode == 1)
-        launch(K_GEMM_LO, flops, bytes, k_gemm_grouped_lo<1>, grid, dim3(256), 0, b, groups, tile_group, terms, ntiles);
-    else if (split)
-        launch(K_GEMM_LO, flops, bytes, k_gemm_grouped_lo_split<2>, grid, dim3(256), 0, b, groups, tile_group, terms);
+    if (waves != 0 && waves != 4 && waves != 8 && waves != 16)
+        throw Error{MPSPT_E_ARG, "grouped GEMM: waves per tile must be 0, 4, 8 or 16"};
+    if (mode == 1)
+        gemm_lo_launch<1>(b, groups, tile_group, terms, ntiles, waves, flops, bytes);
     else
-        launch(K_GEMM_LO, flops, bytes, k_gemm_grouped_lo<2>, grid, dim3(256), 0, b, groups, tile_group, terms, ntiles);
+        gemm_lo_launch<2>(b, groups, tile_group, terms, ntiles, waves, flops, bytes);
     check(hipGetLastError(), "k_gemm_grouped_lo");
 }
 void axpy_grouped_lo(const BasesF& b, const AxpyGroup* groups, int ngroups, const AxpyTerm* terms, double flops,

@@ -152,7 +152,7 @@ class Context:
         if os.path.exists(TUNING_PATH):
             with open(TUNING_PATH) as f:
                 t = json.load(f)["choice"]
-            self.set_tuning(t["wide_chunks"], t["kseg_min"], t["kseg_div"])
+            self.set_tuning(t["wide_chunks"], t["kseg_min"], t["kseg_div"], t.get("split_waves", 4))
 
     def close(self):
         if getattr(self, "h", None):
@@ -269,13 +269,13 @@ class Context:
                                                 t.ctypes.data_as(C.POINTER(C.c_float)), C.byref(n)))
         return X, t
 
-    def set_tuning(self, wide_chunks, kseg_min, kseg_div):
-        self._ok(self.lib.mpspt_set_tuning(self.h, int(wide_chunks), int(kseg_min), int(kseg_div)))
+    def set_tuning(self, wide_chunks, kseg_min, kseg_div, split_waves=4):
+        self._ok(self.lib.mpspt_set_tuning(self.h, int(wide_chunks), int(kseg_min), int(kseg_div), int(split_waves)))
 
     def get_tuning(self):
-        a, b, c = C.c_int32(), C.c_int32(), C.c_int32()
-        self._ok(self.lib.mpspt_get_tuning(self.h, C.byref(a), C.byref(b), C.byref(c)))
-        return {"wide_chunks": a.value, "kseg_min": b.value, "kseg_div": c.value}
+        a, b, c, d = C.c_int32(), C.c_int32(), C.c_int32(), C.c_int32()
+        self._ok(self.lib.mpspt_get_tuning(self.h, C.byref(a), C.byref(b), C.byref(c), C.byref(d)))
+        return {"wide_chunks": a.value, "kseg_min": b.value, "kseg_div": c.value, "split_waves": d.value}
 
     def profile(self, enable=True, every=1):
         """Record kernel durations (every ``every``-th launch of each kind), or stop."""

@@ -314,19 +314,20 @@ def test_size_limits(mp):
 def test_launch_shapes_and_split_k(mp, c1):
     """The grouped GEMM's launch shapes and split-k segments change how the
     same sums are tiled and ordered, not what is summed: forcing every list
-    to one wave per tile, or to one workgroup per tile, with or without heavy
-    k splitting, gives the same running E2 and bond tables as the defaults
-    (and the oracle) to rounding."""
+    to one wave per tile, or to one workgroup of 4, 8 or 16 waves per tile,
+    with or without heavy k splitting, gives the same running E2 and bond
+    tables as the defaults (and the oracle) to rounding."""
     ints, eri, psi0, ref = c1
     print("case: 4a+4v M1=8 launch shapes x split-k", flush=True)
     g = inputs.psi1_guess(4, 4, 4, 0, 8, 1000)
     sw = mps.Sweeper(ints.h, eri, 4, ints.eps_virt, 4, 0, psi0, (g.bonds, g.sites), 8)
     sw.run()
     oref = [t["e2"] for t in sw.trace]
-    for wide, kmin, kdiv in ((8, 512, 8192), (1, 512, 8192), (1 << 20, 512, 8192), (1, 16, 1), (1 << 20, 16, 1)):
+    for wide, kmin, kdiv, waves in ((8, 512, 8192, 4), (1, 512, 8192, 4), (1 << 20, 512, 8192, 4), (1, 16, 1, 4),
+                                    (1 << 20, 16, 1, 4), (1, 512, 8192, 8), (1, 512, 8192, 16), (1, 16, 1, 16)):
         ctx = mp.Context(0)
-        ctx.set_tuning(wide, kmin, kdiv)
-        assert ctx.get_tuning() == {"wide_chunks": wide, "kseg_min": kmin, "kseg_div": kdiv}
+        ctx.set_tuning(wide, kmin, kdiv, waves)
+        assert ctx.get_tuning() == {"wide_chunks": wide, "kseg_min": kmin, "kseg_div": kdiv, "split_waves": waves}
         ctx.load_integrals(4, 4, ints.h, ints.B)
         ctx.load_h0_partition(ints.eps_virt)
         ctx.load_psi0(4, 0, *psi0)
@@ -334,6 +335,8 @@ def test_launch_shapes_and_split_k(mp, c1):
         ctx.sweep(8)
         np.testing.assert_allclose(ctx.get_trace()["e2"], oref, rtol=0, atol=1e-9)
         for b, ob in enumerate(sw.bonds()):
-            assert ctx.get_bond(0, b) == [(tuple(q), d) for q, d in ob], (wide, kmin, kdiv, b)
+            assert ctx.get_bond(0, b) == [(tuple(q), d) for q, d in ob], (wide, kmin, kdiv, waves, b)
     with pytest.raises(mp.MPSPTError):
         ctx.set_tuning(0, 512, 8192)
+    with pytest.raises(mp.MPSPTError):
+        ctx.set_tuning(4, 512, 8192, 6)
