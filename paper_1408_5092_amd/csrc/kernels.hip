@@ -387,16 +387,39 @@ __global__ __launch_bounds__(256) void k_diag_grouped(Bases bs, const DiagGroup*
 constexpr int EIG_MAXN = 512;
 constexpr double EIG_EPS = 2.220446049250313e-16;
 
+// Cross-lane moves through DPP (no LDS round trip), on both halves of a
+// double; lanes that the control does not write (rows outside ROWS) get 0.
+template <int CTRL, int ROWS = 0xF>
+__device__ __forceinline__ double dpp_f64(double x) {
+    const unsigned long long b = (unsigned long long)__double_as_longlong(x);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)b, CTRL, ROWS, 0xF, true);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(b >> 32), CTRL, ROWS, 0xF, true);
+    return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+
+// Sum over each aligned group of 8 lanes (all 8 active), the same bits in
+// all of them: every step adds a lane's value to its partner's in either
+// order, and a + b == b + a.  DPP controls: quad_perm [1,0,3,2] and
+// [2,3,0,1], then row_half_mirror.
 __device__ __forceinline__ double group8_sum(double v) {
-    v += __shfl_down(v, 4, 8);
-    v += __shfl_down(v, 2, 8);
-    v += __shfl_down(v, 1, 8);
+    v += dpp_f64<0xB1>(v);
+    v += dpp_f64<0x4E>(v);
+    v += dpp_f64<0x141>(v);
     return v;
 }
 
+// Sum over a full wave, the same bits in every lane: 8-lane sums, row_mirror
+// for the 16-lane rows, row_bcast:15 and row_bcast:31 to gather the rows in
+// lane 63, which every lane then reads.
 __device__ __forceinline__ double wave_sum(double v) {
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-    return v;
+    v = group8_sum(v);
+    v += dpp_f64<0x140>(v);
+    v += dpp_f64<0x142, 0xA>(v);
+    v += dpp_f64<0x143, 0xC>(v);
+    const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)(unsigned)b, 63);
+    const int hi = __builtin_amdgcn_readlane((int)(unsigned)(b >> 32), 63);
+    return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
 }
 
 template <bool LDSRES>
@@ -417,8 +440,9 @@ __global__ __launch_bounds__(1024) void k_eig_reduce(const EigJob* __restrict__ 
         }
     }
     __syncthreads();
-    // ---- Householder: wave 0 forms the reflector (and stores it in V), all
-    // threads form p = tau A22 v, then every wave computes K = tau p.v / 2
+    // ---- Householder: wave 0 forms the reflector (v in the column it
+    // annihilates, which no later step reads; copied to V after the loop),
+    // all threads form p = tau A22 v, then every wave computes K = tau p.v / 2
     // itself and applies A22 -= v w^T + w v^T with w = p - K v.
     for (int k = 0; k + 2 < n; ++k) {
         const int m = n - k - 1;
@@ -436,13 +460,12 @@ __global__ __launch_bounds__(1024) void k_eig_reduce(const EigJob* __restrict__ 
             for (int i = k + 1 + lane; i < n; i += 64) {
                 const double vi = (i == k + 1) ? 1.0 : M[i * ld + k] * scal;
                 sv[i] = vi;
-                if (i >= k + 2) V[(size_t)k * n + i] = vi;
+                if (i >= k + 2) M[i * ld + k] = vi;
             }
             if (lane == 0) {
                 sd[k] = M[k * ld + k];
                 se[k] = beta;
                 stau[k] = tau;
-                V[(size_t)k * n + k] = tau;
             }
         }
         __syncthreads();
@@ -480,6 +503,16 @@ __global__ __launch_bounds__(1024) void k_eig_reduce(const EigJob* __restrict__ 
     for (int i = tid; i < n; i += 1024) {
         J.t[i] = sd[i];
         J.t[n + i] = se[i];
+    }
+    // the reflectors: row r of V holds tau_r at r and v_r below r + 1
+    for (int e = tid; e < n * n; e += 1024) {
+        const int r = e / n, i = e - r * n;
+        if (r + 2 < n) {
+            if (i >= r + 2)
+                V[e] = M[i * ld + r];
+            else if (i == r)
+                V[e] = stau[r];
+        }
     }
     // ---- Gershgorin bracket, pivot guard and tolerance (wave 0); sp <- e^2
     if (tid < 64) {
@@ -524,15 +557,28 @@ __global__ __launch_bounds__(1024) void k_eig_reduce(const EigJob* __restrict__ 
             double q = sd[0] - x;
             if (fabs(q) <= piv) q = -piv;
             cnt = q < 0.0;
-            for (int i = 1; i < n; ++i) {
-                // hardware reciprocal refined by one Newton step: each count
-                // stays the exact count of a matrix within a few ulps of T
+            // hardware reciprocal refined by one Newton step: each count
+            // stays the exact count of a matrix within a few ulps of T; the
+            // LDS reads of eight steps are issued ahead of their chain
+            auto sturm = [&](double dv, double ev) {
                 double r = __builtin_amdgcn_rcp(q);
                 r = fma(r, fma(-q, r, 1.0), r);
-                q = sd[i] - x - sp[i - 1] * r;
+                q = dv - x - ev * r;
                 if (fabs(q) <= piv) q = -piv;
                 cnt += q < 0.0;
+            };
+            int i = 1;
+            for (; i + 8 <= n; i += 8) {
+                double dv[8], ev[8];
+#pragma unroll
+                for (int t = 0; t < 8; ++t) {
+                    dv[t] = sd[i + t];
+                    ev[t] = sp[i + t - 1];
+                }
+#pragma unroll
+                for (int t = 0; t < 8; ++t) sturm(dv[t], ev[t]);
             }
+            for (; i < n; ++i) sturm(sd[i], sp[i - 1]);
         }
         const unsigned long long bal = __ballot(!done && cnt > j);
         const int base = lane - u;
@@ -556,6 +602,16 @@ __device__ __forceinline__ unsigned long long mix64(unsigned long long z) {
     return z ^ (z >> 31);
 }
 
+// 1 / b (b finite and nonzero) to about an ulp: the hardware reciprocal and
+// two Newton steps, a shorter dependent chain than a correctly rounded
+// division.
+__device__ __forceinline__ double recip(double b) {
+    double r = __builtin_amdgcn_rcp(b);
+    r = fma(r, fma(-b, r, 1.0), r);
+    r = fma(r, fma(-b, r, 1.0), r);
+    return r;
+}
+
 // Solves (T - sigma I) y = y in place by Gaussian elimination with partial
 // pivoting (pivots below `guard` in magnitude are raised to it); U's rows go to
 // the thread's scratch columns.  Y(i) addresses the vector.
@@ -568,7 +624,7 @@ __device__ void tri_solve(const double* sd, const double* se, int n, double sigm
         double* Ui = U + (size_t)3 * i * ustride;
         if (fabs(bi) >= fabs(a1)) {
             if (fabs(bi) < guard) bi = bi < 0.0 ? -guard : guard;
-            const double f = a1 / bi;
+            const double f = a1 * recip(bi);
             Ui[0] = bi;
             Ui[ustride] = ci;
             Ui[2 * ustride] = 0.0;
@@ -577,7 +633,7 @@ __device__ void tri_solve(const double* sd, const double* se, int n, double sigm
             ci = c1;
             yi = y1 - f * yi;
         } else {
-            const double f = bi / a1;
+            const double f = bi * recip(a1);
             Ui[0] = a1;
             Ui[ustride] = b1;
             Ui[2 * ustride] = c1;
@@ -589,7 +645,7 @@ __device__ void tri_solve(const double* sd, const double* se, int n, double sigm
         }
     }
     if (fabs(bi) < guard) bi = bi < 0.0 ? -guard : guard;
-    double y2 = 0.0, y1 = yi / bi;
+    double y2 = 0.0, y1 = yi * recip(bi);
     Y(n - 1) = y1;
     // back substitution, the rows of U and y for four steps loaded up front
     int i = n - 2;
@@ -605,7 +661,7 @@ __device__ void tri_solve(const double* sd, const double* se, int n, double sigm
         }
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-            const double y0 = (yv[q] - u1[q] * y1 - u2[q] * y2) / u0[q];
+            const double y0 = (yv[q] - u1[q] * y1 - u2[q] * y2) * recip(u0[q]);
             Y(i - q) = y0;
             y2 = y1;
             y1 = y0;
@@ -613,7 +669,7 @@ __device__ void tri_solve(const double* sd, const double* se, int n, double sigm
     }
     for (; i >= 0; --i) {
         const double* Ui = U + (size_t)3 * i * ustride;
-        const double y0 = (Y(i) - Ui[ustride] * y1 - Ui[2 * ustride] * y2) / Ui[0];
+        const double y0 = (Y(i) - Ui[ustride] * y1 - Ui[2 * ustride] * y2) * recip(Ui[0]);
         Y(i) = y0;
         y2 = y1;
         y1 = y0;
