@@ -451,22 +451,26 @@ void GemmBatch::upload_lists() {
     // launch shape: one workgroup per tile, k spread over its waves, once some
     // tile of the list has a long enough k chain
     waves_ = maxc >= dev::tuning().wide_chunks ? dev::tuning().split_waves : 0;
-    dg_.upload(g_);
-    dt_.upload(t_);
-    dtg_.upload(tg);
-    red_.upload();
+    Packer pk;
+    const size_t og = pk.add(g_), ot = pk.add(t_), otg = pk.add(tg);
+    red_.pack(pk);
+    buf_.upload(pk.bytes());
+    dg_ = reinterpret_cast<const dev::GemmGroup*>(buf_.p + og);
+    dt_ = reinterpret_cast<const dev::GemmTerm*>(buf_.p + ot);
+    dtg_ = reinterpret_cast<const int*>(buf_.p + otg);
+    red_.attach(buf_.p);
 }
 void GemmBatch::run() const {
     dev::Bases b = slots_.bases();
     b.p[kPartSlot] = part_.p;
-    if (tiles_ > 0) dev::gemm_grouped(b, dg_.p, dtg_.p, dt_.p, tiles_, waves_, flops_, bytes_);
+    if (tiles_ > 0) dev::gemm_grouped(b, dg_, dtg_, dt_, tiles_, waves_, flops_, bytes_);
     red_.run(b);
 }
 void GemmBatch::run_lo(const dev::BasesF& b, int mode) const {
     if (abs_) throw err(MPSPT_E_STATE, "reduced-precision work list refers outside its bound buffers");
     dev::BasesF c = b;
     c.p[kPartSlot] = reinterpret_cast<float*>(part_.p);
-    if (tiles_ > 0) dev::gemm_grouped_lo(c, mode, dg_.p, dtg_.p, dt_.p, tiles_, waves_, flops_, bytes_ / 2);
+    if (tiles_ > 0) dev::gemm_grouped_lo(c, mode, dg_, dtg_, dt_, tiles_, waves_, flops_, bytes_ / 2);
     red_.run_lo(c);
 }
 
@@ -509,20 +513,30 @@ void AxpyBatch::term_ref(int8_t slot, int64_t off, int lds, bool trans, double a
     flops_ += 2.0 * g.m * g.n;
     bytes_ += 8.0 * g.m * g.n;
 }
-void AxpyBatch::upload() {
+void AxpyBatch::pack(Packer& pk) {
     std::vector<dev::AxpyGroup> keep;
     for (auto& g : g_)
         if (g.m > 0 && g.n > 0) keep.push_back(g);
     g_.swap(keep);
-    dg_.upload(g_);
-    dt_.upload(t_);
+    og_ = pk.add(g_);
+    ot_ = pk.add(t_);
+}
+void AxpyBatch::attach(const char* dev_base) {
+    dg_ = reinterpret_cast<const dev::AxpyGroup*>(dev_base + og_);
+    dt_ = reinterpret_cast<const dev::AxpyTerm*>(dev_base + ot_);
+}
+void AxpyBatch::upload() {
+    Packer pk;
+    pack(pk);
+    buf_.upload(pk.bytes());
+    attach(buf_.p);
 }
 void AxpyBatch::run(const dev::Bases& b) const {
-    if (!g_.empty()) dev::axpy_grouped(b, dg_.p, (int)g_.size(), dt_.p, flops_, bytes_);
+    if (!g_.empty()) dev::axpy_grouped(b, dg_, (int)g_.size(), dt_, flops_, bytes_);
 }
 void AxpyBatch::run_lo(const dev::BasesF& b) const {
     if (abs_) throw err(MPSPT_E_STATE, "reduced-precision work list refers outside its bound buffers");
-    if (!g_.empty()) dev::axpy_grouped_lo(b, dg_.p, (int)g_.size(), dt_.p, flops_, bytes_ / 2);
+    if (!g_.empty()) dev::axpy_grouped_lo(b, dg_, (int)g_.size(), dt_, flops_, bytes_ / 2);
 }
 
 // ------------------------------------------------------------- inputs

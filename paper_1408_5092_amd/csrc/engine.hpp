@@ -6,6 +6,7 @@
 #include <memory>
 #include <set>
 #include <string>
+#include <cstring>
 #include <vector>
 
 #include "device.hpp"
@@ -51,6 +52,23 @@ class DevArr {
     }
     T* p = nullptr;
     size_t cap = 0;
+};
+
+// Host arrays staged back to back (each on a 256-byte boundary) so that a
+// work list reaches the device in one copy.
+class Packer {
+  public:
+    template <class T>
+    size_t add(const std::vector<T>& v) {
+        const size_t off = (h_.size() + 255) & ~size_t(255);
+        h_.resize(off + v.size() * sizeof(T));
+        if (!v.empty()) std::memcpy(h_.data() + off, v.data(), v.size() * sizeof(T));
+        return off;
+    }
+    const std::vector<char>& bytes() const { return h_; }
+
+  private:
+    std::vector<char> h_;
 };
 
 struct Bond {
@@ -149,6 +167,10 @@ class AxpyBatch {
     void term_ref(int8_t slot, int64_t off, int lds, bool trans, double alpha);
     void reserve(size_t groups, size_t terms) { g_.reserve(groups); t_.reserve(terms); }
     void upload();
+    // upload() in two halves, for a list that travels inside another's copy:
+    // stage the groups and terms, then point at their device copy
+    void pack(Packer& pk);
+    void attach(const char* dev_base);
     void run() const { run(slots_.bases()); }
     void run(const dev::Bases& b) const;
     void run_lo(const dev::BasesF& b) const;  // FP32 copies of the slots
@@ -160,8 +182,10 @@ class AxpyBatch {
     SlotMap slots_;
     std::vector<dev::AxpyGroup> g_;
     std::vector<dev::AxpyTerm> t_;
-    DevArr<dev::AxpyGroup> dg_;
-    DevArr<dev::AxpyTerm> dt_;
+    DevArr<char> buf_;  // groups and terms, one copy
+    size_t og_ = 0, ot_ = 0;
+    const dev::AxpyGroup* dg_ = nullptr;
+    const dev::AxpyTerm* dt_ = nullptr;
     double flops_ = 0, bytes_ = 0;
     bool abs_ = false;  // some reference lies outside the bound slots
 };
@@ -189,9 +213,10 @@ class GemmBatch {
     SlotMap slots_;
     std::vector<dev::GemmGroup> g_;
     std::vector<dev::GemmTerm> t_;
-    DevArr<dev::GemmGroup> dg_;
-    DevArr<dev::GemmTerm> dt_;
-    DevArr<int> dtg_;    // tile -> group
+    DevArr<char> buf_;  // groups, terms, tile -> group map and the split-k sums' lists, one copy
+    const dev::GemmGroup* dg_ = nullptr;
+    const dev::GemmTerm* dt_ = nullptr;
+    const int* dtg_ = nullptr;
     int waves_ = 0;  // launch shape: waves per tile's workgroup (long k chains), 0: one wave per tile
     int tiles_ = 0;
     double flops_ = 0, bytes_ = 0;
