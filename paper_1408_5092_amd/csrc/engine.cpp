@@ -1140,10 +1140,12 @@ void Engine::build_effop(EffOp& op, const Env& L, const Env& R, const TwoOp& O, 
         uoff[lb] = usz;
         usz += (size_t)L.blk[lb].rows * ket.pw[ik];
     }
-    // stage 2 layout: V blocks per (bra block, w')
+    // stage 2 layout: V blocks per (bra block, w'), their terms in one flat
+    // list (vts[t0, t1) for a block)
     struct VT { size_t usrc; int lds; double a; };
-    struct VB { int bb, rb; size_t off; int rows, cols; std::vector<VT> t; };
+    struct VB { int bb, rb; size_t off; int rows, cols; size_t t0, t1; };
     std::vector<VB> vbs;
+    std::vector<VT> vts;
     size_t vsz = 0;
     for (size_t bb = 0; bb < bra.blk.size(); ++bb) {
         const auto& Y = bra.blk[bb];
@@ -1151,23 +1153,23 @@ void Engine::build_effop(EffOp& op, const Env& L, const Env& R, const TwoOp& O, 
             const int wp = R.blk[rb].w;
             const auto& terms = O.by_out[(size_t)wp * 16 + Y.s1 * 4 + Y.s2];
             if (terms.empty()) continue;
-            int jrk = R.blk[rb].ik;
-            VB v{(int)bb, rb, 0, Y.rows, R.blk[rb].cols, {}};
+            const int jrk = R.blk[rb].ik;
+            const size_t t0 = vts.size();
             for (const auto& t : terms) {
                 // the L block of channel w at this bra sector fixes the ket sector
                 const int lb = L.find(t.w, Y.il);
                 if (lb < 0 || uoff[lb] == (size_t)-1) continue;
                 const int ik = L.blk[lb].ik;
-                int xb = ket.idx[(ik * 4 + t.s1) * 4 + t.s2];
+                const int xb = ket.idx[(ik * 4 + t.s1) * 4 + t.s2];
                 if (xb < 0 || ket.blk[xb].jr != jrk) continue;
-                v.t.push_back({uoff[lb] + ket.blk[xb].col, ket.pw[ik], t.v});
+                vts.push_back({uoff[lb] + ket.blk[xb].col, ket.pw[ik], t.v});
                 lused[lb] = 1;
             }
-            if (v.t.empty()) continue;
-            v.off = vsz;
-            vsz += (size_t)v.rows * v.cols;
+            if (vts.size() == t0) continue;
+            const int cols = R.blk[rb].cols;
+            vbs.push_back({(int)bb, rb, vsz, Y.rows, cols, t0, vts.size()});
+            vsz += (size_t)Y.rows * cols;
             rused[rb] = 1;
-            vbs.push_back(std::move(v));
         }
     }
     op.U.ensure(std::max<size_t>(usz, 1));
@@ -1181,14 +1183,11 @@ void Engine::build_effop(EffOp& op, const Env& L, const Env& R, const TwoOp& O, 
         op.st1.term(L.data.p + B.off, B.cols, false, xket + ket.po[B.ik], ket.pw[B.ik], false, B.cols, 1.0);
         op.bytes += 8.0 * B.rows * B.cols;
     }
-    {
-        size_t nt = 0;
-        for (const VB& v : vbs) nt += v.t.size();
-        op.st2.reserve(vbs.size(), nt);
-    }
+    // (slot-relative references: U is slot 4, V slot 5)
+    op.st2.reserve(vbs.size(), vts.size());
     for (const VB& v : vbs) {
-        op.st2.group(op.V.p + v.off, v.cols, v.rows, v.cols, false);
-        for (const VT& t : v.t) op.st2.term(op.U.p + t.usrc, t.lds, false, t.a);
+        op.st2.group_ref(5, (int64_t)v.off, v.cols, v.rows, v.cols, false);
+        for (size_t t = v.t0; t < v.t1; ++t) op.st2.term_ref(4, (int64_t)vts[t].usrc, vts[t].lds, false, vts[t].a);
     }
     size_t vi = 0;
     for (size_t bb = 0; bb < bra.blk.size(); ++bb) {
