@@ -8,7 +8,8 @@ a seeded random Psi1 guess at bond dimension guess-m (the sweeps grow it to
 M1), and runs the same sweeps once per precision (0 FP64, 1 FP32, 2 BF16x3
 sigma with FP64 refinement).  Prints one JSON line per precision with E2
 (and E3 with --e3), the difference from the first precision listed, CG
-counts, host phase times and the grouped-GEMM rate from sampled HIP events.
+counts, host phase times and the grouped-GEMM rate (flops and algorithmic
+bytes) from sampled HIP events.
 Argument marshalling only: every step runs in the library's kernels.
 """
 from __future__ import annotations
@@ -64,6 +65,11 @@ def main(argv=None):
             "e3": r["e3"] if a.e3 else None, "cg_iters": r["cg_iters"], "sigma_lo_calls": r["sigma_lo_calls"],
             "refinements": r["refinements"], "flags": r["flags"], "host_phase_seconds": r["t_phase"],
             "gemm_tflops_sampled": sum(s["flops"] for s in gemm) / sec / 1e12 if sec else None,
+            # algorithmic bytes (operand blocks once per term, outputs once) over the recorded time,
+            # and that as a fraction of the 8 TB/s HBM peak
+            "gemm_gbs_sampled": sum(s["bytes"] for s in gemm) / sec / 1e9 if sec else None,
+            "gemm_hbm_frac_sampled": sum(s["bytes"] for s in gemm) / sec / 8e12 if sec else None,
+            "gemm_avg_launch_us": 1e6 * sec / max(1, sum(s["launches"] for s in gemm)),
         }
         if first is None:
             first = out
