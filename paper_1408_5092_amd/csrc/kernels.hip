@@ -243,76 +243,92 @@ __global__ __launch_bounds__(64 * W) void k_gemm_grouped_lo_split(BasesF bs, con
 }
 
 // ------------------------------------------------------------------- AXPY
-// One workgroup per output block.  A block with fewer elements than threads
+// One workgroup per output block.  The block's terms are staged in LDS, up
+// to 256 at a time, as resolved source pointers (one coalesced read of the
+// term records per chunk instead of a dependent scalar load of each record
+// and its slot base per term).  A block with fewer elements than threads
 // deals its terms round-robin to S = min(256 / elements, terms / 4) thread
 // sets (term t to set t % S); each thread sums its terms in list order with
-// eight loads in flight, and the S partial sums of an element are added in
-// set order through LDS, so the result is deterministic.
+// eight loads in flight (a block with more elements keeps its running sums
+// in the output between chunks), and the S partial sums of an element are
+// added in set order through LDS, so the result is deterministic.
+template <typename R>
+struct AxpyTermL {
+    const R* src;
+    R alpha;
+    int lds, trans;
+};
+
 template <typename R, typename BS>
-__device__ inline void axpy_block(const BS& bs, const AxpyGroup& g, const AxpyTerm* __restrict__ T, R* red) {
+__device__ inline void axpy_block(const BS& bs, const AxpyGroup& g, const AxpyTerm* __restrict__ T, R* red,
+                                  AxpyTermL<R>* st) {
     R* dst = bs.p[g.sd] + g.od;
     const int total = g.m * g.n;
     if (total <= 0) return;
     const int S = total >= 256 ? 1 : max(1, min(256 / total, g.nterms / 4));
+    auto stage = [&](int c0) {  // terms c0 .. c0 + 255 of the group into st
+        const int cnt = min(256, g.nterms - c0);
+        __syncthreads();        // the previous chunk's readers are done
+        if ((int)threadIdx.x < cnt) {
+            const AxpyTerm tm = T[g.term0 + c0 + threadIdx.x];
+            st[threadIdx.x] = AxpyTermL<R>{bs.p[tm.ss] + tm.os, (R)tm.alpha, tm.lds, (int)tm.trans};
+        }
+        __syncthreads();
+        return cnt;
+    };
+    auto val = [](const AxpyTermL<R>& tm, int i, int j) {
+        return tm.alpha * (tm.trans ? tm.src[(size_t)j * tm.lds + i] : tm.src[(size_t)i * tm.lds + j]);
+    };
     if (S == 1) {
-        // element e = i n + j, advanced by the block size without dividing
-        const int di = blockDim.x / g.n, dj = blockDim.x - di * g.n;
-        int i = threadIdx.x / g.n, j = threadIdx.x - i * g.n;
-        for (int e = threadIdx.x; e < total; e += blockDim.x) {
-            R s = g.accumulate ? dst[(size_t)i * g.ldd + j] : R(0);
-            int t = 0;
-            for (; t + 8 <= g.nterms; t += 8) {
-                R v[8];
+        for (int c0 = 0; c0 == 0 || c0 < g.nterms; c0 += 256) {
+            const int cnt = stage(c0);
+            // element e = i n + j, advanced by the block size without dividing
+            const int di = blockDim.x / g.n, dj = blockDim.x - di * g.n;
+            int i = threadIdx.x / g.n, j = threadIdx.x - i * g.n;
+            for (int e = threadIdx.x; e < total; e += blockDim.x) {
+                R* d = dst + (size_t)i * g.ldd + j;
+                R s = (c0 > 0 || g.accumulate) ? *d : R(0);
+                int t = 0;
+                for (; t + 8 <= cnt; t += 8) {
+                    R v[8];
 #pragma unroll
-                for (int u = 0; u < 8; ++u) {
-                    const AxpyTerm tm = T[g.term0 + t + u];
-                    const R* src = bs.p[tm.ss] + tm.os;
-                    v[u] = (R)tm.alpha * (tm.trans ? src[(size_t)j * tm.lds + i] : src[(size_t)i * tm.lds + j]);
+                    for (int u = 0; u < 8; ++u) v[u] = val(st[t + u], i, j);
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) s += v[u];
                 }
-#pragma unroll
-                for (int u = 0; u < 8; ++u) s += v[u];
-            }
-            for (; t < g.nterms; ++t) {
-                const AxpyTerm tm = T[g.term0 + t];
-                const R* src = bs.p[tm.ss] + tm.os;
-                s += (R)tm.alpha * (tm.trans ? src[(size_t)j * tm.lds + i] : src[(size_t)i * tm.lds + j]);
-            }
-            dst[(size_t)i * g.ldd + j] = s;
-            i += di;
-            j += dj;
-            if (j >= g.n) {
-                j -= g.n;
-                ++i;
+                for (; t < cnt; ++t) s += val(st[t], i, j);
+                *d = s;
+                i += di;
+                j += dj;
+                if (j >= g.n) {
+                    j -= g.n;
+                    ++i;
+                }
             }
         }
         return;
     }
     const int e = threadIdx.x % total, set = threadIdx.x / total;
+    const int i = e / g.n, j = e - i * g.n;
     R s = R(0);
-    if (set < S) {
-        const int i = e / g.n, j = e - i * g.n;
-        int t = set;
-        for (; t + 7 * S < g.nterms; t += 8 * S) {
-            R v[8];
+    for (int c0 = 0; c0 < g.nterms; c0 += 256) {
+        const int cnt = stage(c0);
+        if (set < S) {
+            // this set's terms in the chunk: global index c0 + t with (c0 + t) % S == set
+            int t = (set - c0 % S + S) % S;
+            for (; t + 7 * S < cnt; t += 8 * S) {
+                R v[8];
 #pragma unroll
-            for (int u = 0; u < 8; ++u) {
-                const AxpyTerm tm = T[g.term0 + t + u * S];
-                const R* src = bs.p[tm.ss] + tm.os;
-                v[u] = (R)tm.alpha * (tm.trans ? src[(size_t)j * tm.lds + i] : src[(size_t)i * tm.lds + j]);
+                for (int u = 0; u < 8; ++u) v[u] = val(st[t + u * S], i, j);
+#pragma unroll
+                for (int u = 0; u < 8; ++u) s += v[u];
             }
-#pragma unroll
-            for (int u = 0; u < 8; ++u) s += v[u];
-        }
-        for (; t < g.nterms; t += S) {
-            const AxpyTerm tm = T[g.term0 + t];
-            const R* src = bs.p[tm.ss] + tm.os;
-            s += (R)tm.alpha * (tm.trans ? src[(size_t)j * tm.lds + i] : src[(size_t)i * tm.lds + j]);
+            for (; t < cnt; t += S) s += val(st[t], i, j);
         }
     }
     red[threadIdx.x] = s;
     __syncthreads();
-    if (threadIdx.x < total) {
-        const int i = e / g.n, j = e - i * g.n;
+    if ((int)threadIdx.x < total) {
         R acc = g.accumulate ? dst[(size_t)i * g.ldd + j] : R(0);
         for (int q = 0; q < S; ++q) acc += red[q * total + e];
         dst[(size_t)i * g.ldd + j] = acc;
@@ -322,7 +338,8 @@ __device__ inline void axpy_block(const BS& bs, const AxpyGroup& g, const AxpyTe
 __global__ __launch_bounds__(256) void k_axpy_grouped(Bases bs, const AxpyGroup* __restrict__ G,
                                                       const AxpyTerm* __restrict__ T) {
     __shared__ double red[256];
-    axpy_block<double>(bs, G[blockIdx.x], T, red);
+    __shared__ AxpyTermL<double> st[256];
+    axpy_block<double>(bs, G[blockIdx.x], T, red, st);
 }
 
 // ------------------------------------------------- reduced-precision sigma
@@ -332,7 +349,8 @@ __global__ __launch_bounds__(256) void k_axpy_grouped(Bases bs, const AxpyGroup*
 __global__ __launch_bounds__(256) void k_axpy_grouped_lo(BasesF bs, const AxpyGroup* __restrict__ G,
                                                          const AxpyTerm* __restrict__ T) {
     __shared__ float red[256];
-    axpy_block<float>(bs, G[blockIdx.x], T, red);
+    __shared__ AxpyTermL<float> st[256];
+    axpy_block<float>(bs, G[blockIdx.x], T, red, st);
 }
 
 __global__ __launch_bounds__(256) void k_to_f32(float* __restrict__ dst, const double* __restrict__ src, size_t n) {
