@@ -45,3 +45,18 @@ def test_stored_pair_shares_add_up_to_stored_e2():
         a, b = s["pair"]
         share = {(x, y): e for x, y, e in pg["share"]}[(a, b)]
         assert s["e2_sweep"][-1] >= share  # truncated sweep: Hylleraas upper bound
+
+
+def test_tuning_file_matches_the_binding():
+    """The committed launch-shape table has the keys Context applies, within
+    the ranges mpspt_set_tuning accepts."""
+    import json
+    import os
+    from paper_1408_5092_amd import autotune, mpspt
+    with open(mpspt.TUNING_PATH) as f:
+        t = json.load(f)
+    choice = t["choice"]
+    assert set(choice) == set(autotune.DEFAULT) == set(autotune.GRID)
+    assert choice["wide_chunks"] >= 1 and choice["kseg_min"] >= 16 and choice["kseg_div"] >= 1
+    assert choice["split_waves"] in (4, 8, 16)
+    assert os.path.dirname(mpspt.TUNING_PATH) == os.path.dirname(os.path.abspath(mpspt.__file__))
