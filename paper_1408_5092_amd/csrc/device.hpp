@@ -177,9 +177,11 @@ void cg_init(double* r, double* z, double* p, const double* b, const double* q, 
 // q -= shift * p ; scal[PQ] = p.q
 void cg_shift_dot(double* q, const double* p, double shift, size_t n, double* scal, double* partials);
 // alpha = rz_cur / pq (0 if pq = 0) ; x += alpha p ; r -= alpha q ; z = r / d ;
-// scal[rz_new] = r.z ; scal[RR] = r.r
+// scal[rz_new] = r.z ; scal[RR] = r.r ; host_out (pinned, from host_alloc;
+// may be null) receives scal[0 .. S_N) once the sums are in, readable after
+// an event recorded behind the launch has completed
 void cg_update(double* x, double* r, double* z, const double* p, const double* q, const double* d,
-               size_t n, double* scal, int rz_cur, int rz_new, double* partials);
+               size_t n, double* scal, int rz_cur, int rz_new, double* partials, double* host_out = nullptr);
 // p = z + (rz_new / rz_cur) p (beta = 0 if rz_cur = 0)
 void cg_direction(double* p, const double* z, size_t n, const double* scal, int rz_cur, int rz_new);
 // y = a x + b y

@@ -1687,7 +1687,8 @@ int Engine::solve(int i, double& e2) {
         // starting residual by inner_rel_tol, or at the final tolerance
         const double stop2 = std::max(cg_tol2_ * bb, inner_tol2_ * rr);
         if (lo) dev::to_f32(fb.p[2], p_.p, n);
-        // Iteration k's scalars go to pinned slot k % 2; the host examines
+        // Iteration k's scalars go to pinned slot k % 2 (the update kernel
+        // writes them there itself); the host examines
         // iteration k - 1 while iteration k runs, so the device never waits
         // for the host.  When k - 1 has converged, x carries the one extra
         // iteration k.
@@ -1701,8 +1702,8 @@ int Engine::solve(int i, double& e2) {
         while (!conv) {
             if (it < cg_max_) {
                 apply_inner();
-                dev::cg_update(x_.p, r_.p, z_.p, p_.p, q_.p, d_.p, n, scal_.p, cur, nxt, partials_.p);
-                dev::d2h_async(hsc_ + (it & 1) * dev::S_N, scal_.p, dev::S_N * sizeof(double));
+                dev::cg_update(x_.p, r_.p, z_.p, p_.p, q_.p, d_.p, n, scal_.p, cur, nxt, partials_.p,
+                               hsc_ + (it & 1) * dev::S_N);
                 dev::event_record(ev_[it & 1]);
                 if (lo) dev::cg_direction_lo(p_.p, fb.p[2], z_.p, n, scal_.p, cur, nxt);
                 else dev::cg_direction(p_.p, z_.p, n, scal_.p, cur, nxt);

@@ -944,8 +944,9 @@ inline int n_blocks(size_t n) {
 // part[v * kPartials / 4 + block]; the last block to arrive (counted at
 // part + kPartials) adds each row in block order, writes scal[slots[v]] and
 // resets the counter.  The order of every addition is fixed.
+// Returns true in the block that wrote the sums (the last to arrive).
 template <int NV>
-__device__ void reduce_rows(const double (&v)[NV], double* part, double* scal, const int (&slots)[NV]) {
+__device__ bool reduce_rows(const double (&v)[NV], double* part, double* scal, const int (&slots)[NV]) {
     __shared__ double red[RED_THREADS];
     __shared__ int last;
     constexpr int stride = kPartials / 4;
@@ -959,7 +960,7 @@ __device__ void reduce_rows(const double (&v)[NV], double* part, double* scal, c
         last = atomicAdd(counter, 1) == (int)gridDim.x - 1;
     }
     __syncthreads();
-    if (!last) return;
+    if (!last) return false;
     __threadfence();
     for (int r = 0; r < NV; ++r) {
         double sacc = 0.0;
@@ -968,6 +969,7 @@ __device__ void reduce_rows(const double (&v)[NV], double* part, double* scal, c
         __syncthreads();
     }
     if (threadIdx.x == 0) *counter = 0;
+    return true;
 }
 
 // Thread t of block b covers elements b*RED_THREADS + t + k*(nb*RED_THREADS).
@@ -1010,7 +1012,8 @@ __global__ __launch_bounds__(RED_THREADS) void k_shift_dot(double* q, const doub
 // alpha = rz / pq (0 when pq is 0: a search direction that vanished)
 __global__ __launch_bounds__(RED_THREADS) void k_cg_update(double* x, double* r, double* z, const double* p,
                                                            const double* q, const double* d, size_t n,
-                                                           double* scal, int rz_cur, int rz_new, double* part) {
+                                                           double* scal, int rz_cur, int rz_new, double* part,
+                                                           double* host_out) {
     const double pq = scal[S_PQ];
     const double alpha = pq != 0.0 ? scal[rz_cur] / pq : 0.0;
     double rz = 0.0, rr = 0.0;
@@ -1023,7 +1026,13 @@ __global__ __launch_bounds__(RED_THREADS) void k_cg_update(double* x, double* r,
         rz += rv * zv;
         rr += rv * rv;
     }
-    reduce_rows<2>({rz, rr}, part, scal, {rz_new, (int)S_RR});
+    const bool last = reduce_rows<2>({rz, rr}, part, scal, {rz_new, (int)S_RR});
+    // the scalars also go to the caller's pinned host buffer (its thread 0
+    // wrote the new sums itself), flushed to system scope
+    if (last && host_out != nullptr && threadIdx.x == 0) {
+        for (int sl = 0; sl < S_N; ++sl) host_out[sl] = scal[sl];
+        __threadfence_system();
+    }
 }
 
 __global__ __launch_bounds__(RED_THREADS) void k_cg_direction(double* p, const double* z, size_t n,
@@ -1451,10 +1460,10 @@ void cg_shift_dot(double* q, const double* p, double shift, size_t n, double* sc
     check(hipGetLastError(), "cg_shift_dot");
 }
 void cg_update(double* x, double* r, double* z, const double* p, const double* q, const double* d, size_t n,
-               double* scal, int rz_cur, int rz_new, double* partials) {
+               double* scal, int rz_cur, int rz_new, double* partials, double* host_out) {
     const int nb = n_blocks(n);
     launch(K_VEC, 9.0 * n, 64.0 * n, k_cg_update, dim3(nb), dim3(RED_THREADS), 0, x, r, z, p, q, d, n, scal, rz_cur,
-           rz_new, partials);
+           rz_new, partials, host_out);
     check(hipGetLastError(), "cg_update");
 }
 void cg_direction(double* p, const double* z, size_t n, const double* scal, int rz_cur, int rz_new) {
