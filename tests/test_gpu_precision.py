@@ -10,6 +10,8 @@ solve ends on the same FP64 residual test as the plain FP64 path.  So:
 * 8 active + 16 virtual orbitals, M1 = 128, four sweeps (the benchmarked
   workload): E2 per sweep and E3 match the stored oracle values to 1e-6 Eh,
   and the FP64 GPU run to 1e-8 Eh (the difference is printed per energy);
+* every launch shape of the reduced-precision GEMM (4 or 16 waves per tile,
+  heavy split-k) matches the oracle on the small system;
 * bad precision arguments are refused.
 """
 import json
@@ -108,6 +110,30 @@ def test_benchmark_workload(mp, c2, precision):
     assert d_sweep < 1e-8
     assert abs(res["e3"] - ref["e3"]) < 1e-8
     assert res["flags"] == 0
+
+
+@pytest.mark.parametrize("waves", [4, 16])
+@pytest.mark.parametrize("precision", [1, 2])
+def test_reduced_precision_launch_shapes(mp, c1, precision, waves):
+    """The FP32 and BF16x3 GEMM instances in every launch shape: all work
+    lists on one workgroup of 4 or 16 waves per tile with heavy split-k
+    segmenting, same running E2 and bond tables as the oracle's FP64 sweep."""
+    ints, eri, psi0 = c1
+    print(f"case: 4a+4v M1=16 precision {precision}, {waves} waves per tile, split k", flush=True)
+    g = inputs.psi1_guess(4, 4, 4, 0, 16, 1000)
+    ctx = mp.Context(0)
+    ctx.set_tuning(1, 16, 1, waves)
+    ctx.load_integrals(4, 4, ints.h, ints.B)
+    ctx.load_h0_partition(ints.eps_virt)
+    ctx.load_psi0(4, 0, *psi0)
+    ctx.load_psi1_guess(g.bonds, g.sites)
+    res = ctx.sweep(16, precision=precision)
+    sw = mps.Sweeper(ints.h, eri, 4, ints.eps_virt, 4, 0, psi0, (g.bonds, g.sites), 16)
+    sw.run()
+    np.testing.assert_allclose(ctx.get_trace()["e2"], [t["e2"] for t in sw.trace], rtol=0, atol=1e-9)
+    for b, ob in enumerate(sw.bonds()):
+        assert ctx.get_bond(0, b) == [(tuple(q), d) for q, d in ob], f"bond {b}"
+    assert res["flags"] == 0 and res["sigma_lo_calls"] > 0
 
 
 def test_bad_precision_arguments(mp, c1):
