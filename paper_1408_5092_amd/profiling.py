@@ -30,7 +30,7 @@ import sys
 
 
 def _short(name):
-    m = re.search(r"(k_\w+(<\w+>)?|__amd_\w+)", name)
+    m = re.search(r"(k_\w+(<[\w, ]+>)?|__amd_\w+)", name)
     return m.group(1) if m else name[:60]
 
 
