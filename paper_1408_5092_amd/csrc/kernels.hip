@@ -58,7 +58,9 @@ typedef double d4 __attribute__((ext_vector_type(4)));
 //                         chains.
 // No LDS staging of operands: each lane loads its MFMA operands straight from
 // global memory, two chunks in flight; rows, columns and k beyond the block
-// load as zeros.  Results are deterministic for either shape.
+// read the block's last row, column or k index (so every load is issued
+// without a branch) and are zeroed before the MFMA.  Results are
+// deterministic for either shape.
 // Element types: MODE 0 FP64 (v_mfma_f64_16x16x4f64), 1 FP32
 // (v_mfma_f32_16x16x4f32), 2 BF16x3 on FP32 data (three
 // v_mfma_f32_16x16x16bf16_1k products of head/tail-split operands).
@@ -101,6 +103,9 @@ __device__ inline typename GemmTypes<MODE>::V gemm_tile(const typename GemmTypes
     const int li = lane & 15, lk = lane >> 4;
     const int ar = row0 + li, bc = col0 + li;
     const bool aok = ar < g.m, bok = bc < g.n;
+    // rows and columns past the block load its last row / column (in bounds)
+    // and are zeroed at use, so the loads need no branches
+    const int arc = aok ? ar : g.m - 1, bcc = bok ? bc : g.n - 1;
     V acc = {R(0), R(0), R(0), R(0)};
     int chunk0 = 0;  // chunks of the earlier terms
     for (int ti = 0; ti < g.nterms; ++ti) {
@@ -108,9 +113,9 @@ __device__ inline typename GemmTypes<MODE>::V gemm_tile(const typename GemmTypes
         // element (row, kk) of op(A) at pa[kk * sa]; element (kk, col) of op(B) at pb[kk * sb]
         const R* A = bs.p[tm.sa] + tm.oa;
         const R* B = bs.p[tm.sb] + tm.ob;
-        const R* pa = tm.transA ? A + ar : A + (size_t)ar * tm.lda;
+        const R* pa = tm.transA ? A + arc : A + (size_t)arc * tm.lda;
         const size_t sa = tm.transA ? (size_t)tm.lda : 1;
-        const R* pb = tm.transB ? B + (size_t)bc * tm.ldb : B + bc;
+        const R* pb = tm.transB ? B + (size_t)bcc * tm.ldb : B + bcc;
         const size_t sb = tm.transB ? 1 : (size_t)tm.ldb;
         const R alpha = (R)tm.alpha;
         const int k = tm.k;
@@ -127,8 +132,10 @@ __device__ inline typename GemmTypes<MODE>::V gemm_tile(const typename GemmTypes
                 for (int u = 0; u < 4; ++u) {
                     const int kk = (c + h * cs) * 16 + (MODE == 2 ? 4 * lk + u : 4 * u + lk);
                     const bool in = kk < k;
-                    a[4 * h + u] = (aok && in) ? pa[(size_t)kk * sa] : R(0);
-                    b[4 * h + u] = (bok && in) ? alpha * pb[(size_t)kk * sb] : R(0);
+                    const size_t kc = (size_t)(in ? kk : k - 1);
+                    const R av = pa[kc * sa], bv = pb[kc * sb];
+                    a[4 * h + u] = (aok && in) ? av : R(0);
+                    b[4 * h + u] = (bok && in) ? alpha * bv : R(0);
                 }
             if constexpr (MODE == 0) {
 #pragma unroll
