@@ -49,8 +49,7 @@ typedef double d4 __attribute__((ext_vector_type(4)));
 // 16 x 16 tiles are numbered consecutively and tile_group maps a tile to its
 // group.  A tile sums every term of its group in list order, each term's k
 // range cut into chunks of 16.  Two launch shapes over the same lists:
-//   k_gemm_grouped:       one wave per tile (one tile per workgroup in FP64,
-//                         four in the reduced-precision instances), for
+//   k_gemm_grouped:       one wave per tile (four tiles per workgroup), for
 //                         lists whose tiles have short k chains;
 //   k_gemm_grouped_split: one workgroup of W = 4, 8 or 16 waves per tile,
 //                         the chunks dealt round-robin to the waves (chunk
@@ -186,13 +185,13 @@ __device__ inline void gemm_store(const typename GemmTypes<MODE>::B& bs, const G
     }
 }
 
-template <int MODE, int TPB>
+template <int MODE>
 __device__ inline void gemm_wave_per_tile(const typename GemmTypes<MODE>::B& bs, const GemmGroup* __restrict__ G,
                                           const int* __restrict__ TG, const GemmTerm* __restrict__ T, int ntiles) {
     // the wave index is uniform across the wave: with it in a scalar register
     // the tile's group and term records come through scalar loads
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
-    const int tile = blockIdx.x * TPB + wave;
+    const int tile = blockIdx.x * 4 + wave;
     if (tile >= ntiles) return;
     const GemmGroup g = G[TG[tile]];
     const int tiles_n = (g.n + GEMM_TILE - 1) / GEMM_TILE;
@@ -221,10 +220,10 @@ __device__ inline void gemm_split_tile(const typename GemmTypes<MODE>::B& bs, co
     gemm_store<MODE>(bs, g, row0, col0, lane, acc);
 }
 
-__global__ __launch_bounds__(64) void k_gemm_grouped(Bases bs, const GemmGroup* __restrict__ G,
-                                                     const int* __restrict__ TG, const GemmTerm* __restrict__ T,
-                                                     int ntiles) {
-    gemm_wave_per_tile<0, 1>(bs, G, TG, T, ntiles);
+__global__ __launch_bounds__(256) void k_gemm_grouped(Bases bs, const GemmGroup* __restrict__ G,
+                                                      const int* __restrict__ TG, const GemmTerm* __restrict__ T,
+                                                      int ntiles) {
+    gemm_wave_per_tile<0>(bs, G, TG, T, ntiles);
 }
 
 template <int W>
@@ -239,7 +238,7 @@ template <int MODE>
 __global__ __launch_bounds__(256) void k_gemm_grouped_lo(BasesF bs, const GemmGroup* __restrict__ G,
                                                          const int* __restrict__ TG, const GemmTerm* __restrict__ T,
                                                          int ntiles) {
-    gemm_wave_per_tile<MODE, 4>(bs, G, TG, T, ntiles);
+    gemm_wave_per_tile<MODE>(bs, G, TG, T, ntiles);
 }
 
 template <int MODE, int W>
@@ -1400,8 +1399,8 @@ void gemm_grouped(const Bases& b, const GemmGroup* groups, const int* tile_group
             launch(K_GEMM, flops, bytes, k_gemm_grouped_split<4>, dim3(ntiles), dim3(256), 0, b, groups, tile_group,
                    terms);
     } else
-        launch(K_GEMM, flops, bytes, k_gemm_grouped, dim3(ntiles), dim3(64), 0, b, groups, tile_group, terms,
-               ntiles);
+        launch(K_GEMM, flops, bytes, k_gemm_grouped, dim3((ntiles + 3) / 4), dim3(256), 0, b, groups, tile_group,
+               terms, ntiles);
     check(hipGetLastError(), "k_gemm_grouped");
 }
 void axpy_grouped(const Bases& b, const AxpyGroup* groups, int ngroups, const AxpyTerm* terms, double flops,
