@@ -99,3 +99,26 @@ def test_arguments_are_validated(lib):
     nan[0, 0] = np.nan
     with pytest.raises(mpspt.MPSPTError):
         mpspt.mpo_dims(2, 2, nan, eri, ints.eps_virt, 0, lib=lib)
+
+
+def test_profile_summaries_name_kernels_with_their_template_arguments(tmp_path):
+    """The rocprofv3 summary helper keeps each kernel instance apart (the
+    GEMM's launch shapes and precisions are template arguments) and takes
+    the window between the library's two k_profile_mark dispatches."""
+    from paper_1408_5092_amd import profiling
+    assert profiling._short("void mpspt::dev::(anonymous namespace)::k_gemm_grouped_lo_split<1, 8>(mpspt::dev::BasesF)") \
+        == "k_gemm_grouped_lo_split<1, 8>"
+    assert profiling._short("mpspt::dev::(anonymous namespace)::k_gemm_grouped_split<8>(Bases, ...)") \
+        == "k_gemm_grouped_split<8>"
+    assert profiling._short("k_eig_reduce<true>(EigJob const*)") == "k_eig_reduce<true>"
+    assert profiling._short("__amd_rocclr_copyBuffer") == "__amd_rocclr_copyBuffer"
+    rows = [("k_gemm_grouped(Bases)", 0, 5), ("k_profile_mark(int)", 10, 11), ("k_gemm_grouped(Bases)", 20, 32),
+            ("k_gemm_grouped_split<8>(Bases)", 40, 44), ("k_profile_mark(int)", 50, 51), ("k_dot(double*)", 60, 70)]
+    with open(tmp_path / "run_kernel_trace.csv", "w") as f:
+        f.write("Kernel_Name,Start_Timestamp,End_Timestamp\n")
+        for n, s, e in rows:
+            f.write(f"\"{n}\",{s * 1000},{e * 1000}\n")
+    out = profiling.trace(str(tmp_path))
+    assert out["window_ms"] == pytest.approx(0.040)
+    assert set(out["kernels"]) == {"k_gemm_grouped", "k_gemm_grouped_split<8>"}
+    assert out["kernels"]["k_gemm_grouped"]["avg_us"] == pytest.approx(12.0)
