@@ -1140,12 +1140,11 @@ void Engine::build_effop(EffOp& op, const Env& L, const Env& R, const TwoOp& O, 
         uoff[lb] = usz;
         usz += (size_t)L.blk[lb].rows * ket.pw[ik];
     }
-    // stage 2 layout: V blocks per (bra block, w'), their terms in one flat
-    // list (vts[t0, t1) for a block)
-    struct VT { size_t usrc; int lds; double a; };
-    struct VB { int bb, rb; size_t off; int rows, cols; size_t t0, t1; };
+    // stage 2: V blocks per (bra block, w'), emitted straight into the
+    // middle-stage list as they are found (slot-relative references: U is
+    // slot 4, V slot 5; a block's group is opened at its first term)
+    struct VB { int bb, rb; size_t off; int rows, cols; };
     std::vector<VB> vbs;
-    std::vector<VT> vts;
     size_t vsz = 0;
     for (size_t bb = 0; bb < bra.blk.size(); ++bb) {
         const auto& Y = bra.blk[bb];
@@ -1154,7 +1153,8 @@ void Engine::build_effop(EffOp& op, const Env& L, const Env& R, const TwoOp& O, 
             const auto& terms = O.by_out[(size_t)wp * 16 + Y.s1 * 4 + Y.s2];
             if (terms.empty()) continue;
             const int jrk = R.blk[rb].ik;
-            const size_t t0 = vts.size();
+            const int cols = R.blk[rb].cols;
+            bool open = false;
             for (const auto& t : terms) {
                 // the L block of channel w at this bra sector fixes the ket sector
                 const int lb = L.find(t.w, Y.il);
@@ -1162,12 +1162,15 @@ void Engine::build_effop(EffOp& op, const Env& L, const Env& R, const TwoOp& O, 
                 const int ik = L.blk[lb].ik;
                 const int xb = ket.idx[(ik * 4 + t.s1) * 4 + t.s2];
                 if (xb < 0 || ket.blk[xb].jr != jrk) continue;
-                vts.push_back({uoff[lb] + ket.blk[xb].col, ket.pw[ik], t.v});
+                if (!open) {
+                    op.st2.group_ref(5, (int64_t)vsz, cols, Y.rows, cols, false);
+                    open = true;
+                }
+                op.st2.term_ref(4, (int64_t)(uoff[lb] + ket.blk[xb].col), ket.pw[ik], false, t.v);
                 lused[lb] = 1;
             }
-            if (vts.size() == t0) continue;
-            const int cols = R.blk[rb].cols;
-            vbs.push_back({(int)bb, rb, vsz, Y.rows, cols, t0, vts.size()});
+            if (!open) continue;
+            vbs.push_back({(int)bb, rb, vsz, Y.rows, cols});
             vsz += (size_t)Y.rows * cols;
             rused[rb] = 1;
         }
@@ -1182,12 +1185,6 @@ void Engine::build_effop(EffOp& op, const Env& L, const Env& R, const TwoOp& O, 
         op.st1.group(op.U.p + uoff[lb], ket.pw[B.ik], B.rows, ket.pw[B.ik], false);
         op.st1.term(L.data.p + B.off, B.cols, false, xket + ket.po[B.ik], ket.pw[B.ik], false, B.cols, 1.0);
         op.bytes += 8.0 * B.rows * B.cols;
-    }
-    // (slot-relative references: U is slot 4, V slot 5)
-    op.st2.reserve(vbs.size(), vts.size());
-    for (const VB& v : vbs) {
-        op.st2.group_ref(5, (int64_t)v.off, v.cols, v.rows, v.cols, false);
-        for (size_t t = v.t0; t < v.t1; ++t) op.st2.term_ref(4, (int64_t)vts[t].usrc, vts[t].lds, false, vts[t].a);
     }
     size_t vi = 0;
     for (size_t bb = 0; bb < bra.blk.size(); ++bb) {
