@@ -1146,6 +1146,18 @@ void Engine::build_effop(EffOp& op, const Env& L, const Env& R, const TwoOp& O, 
     struct VB { int bb, rb; size_t off; int rows, cols; };
     std::vector<VB> vbs;
     size_t vsz = 0;
+    {
+        size_t ng = 0, nt = 0;  // upper bounds, for one allocation of each list
+        for (size_t bb = 0; bb < bra.blk.size(); ++bb) {
+            const auto& Y = bra.blk[bb];
+            for (int rb : R.by_ib[Y.jr]) {
+                ++ng;
+                nt += O.by_out[(size_t)R.blk[rb].w * 16 + Y.s1 * 4 + Y.s2].size();
+            }
+        }
+        op.st2.reserve(ng, nt);
+        vbs.reserve(ng);
+    }
     for (size_t bb = 0; bb < bra.blk.size(); ++bb) {
         const auto& Y = bra.blk[bb];
         for (int rb : R.by_ib[Y.jr]) {
