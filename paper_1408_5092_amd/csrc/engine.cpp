@@ -491,7 +491,6 @@ void AxpyBatch::group_ref(int8_t slot, int64_t off, int ldd, int m, int n, bool 
     g.term0 = (int)t_.size();
     g.accumulate = acc ? 1 : 0;
     g_.push_back(g);
-    if (m > 0 && n > 0) bytes_ += 8.0 * m * n * (acc ? 2 : 1);
 }
 void AxpyBatch::term(const double* src, int lds, bool trans, double alpha) {
     int8_t sl;
@@ -510,13 +509,21 @@ void AxpyBatch::term_ref(int8_t slot, int64_t off, int lds, bool trans, double a
     t.alpha = alpha;
     t_.push_back(t);
     ++g.nterms;
-    flops_ += 2.0 * g.m * g.n;
-    bytes_ += 8.0 * g.m * g.n;
 }
 void AxpyBatch::pack(Packer& pk) {
+    // empty groups are dropped here; the counts of the launch (each term
+    // reads its block once, each group writes its block, reading it too
+    // when it accumulates) are taken over the rest, once per list
     std::vector<dev::AxpyGroup> keep;
+    keep.reserve(g_.size());
+    flops_ = bytes_ = 0;
     for (auto& g : g_)
-        if (g.m > 0 && g.n > 0) keep.push_back(g);
+        if (g.m > 0 && g.n > 0) {
+            const double mn = (double)g.m * g.n;
+            flops_ += 2.0 * mn * g.nterms;
+            bytes_ += 8.0 * mn * (g.nterms + (g.accumulate ? 2 : 1));
+            keep.push_back(g);
+        }
     g_.swap(keep);
     og_ = pk.add(g_);
     ot_ = pk.add(t_);

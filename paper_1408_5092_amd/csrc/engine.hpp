@@ -175,7 +175,7 @@ class AxpyBatch {
     void run(const dev::Bases& b) const;
     void run_lo(const dev::BasesF& b) const;  // FP32 copies of the slots
     bool empty() const { return g_.empty(); }
-    double flops() const { return flops_; }
+    double flops() const { return flops_; }  // counted by pack()
     double bytes() const { return bytes_; }
 
   private:
