@@ -277,6 +277,18 @@ TwoOp make_twoop(const MPO& m, int i) {
 }
 
 // ---------------------------------------------------------- work lists
+void Packer::upload(DevArr<char>& buf) const {
+    constexpr size_t kImageMax = 256 << 10;
+    buf.ensure(size_);
+    if (size_ <= kImageMax) {
+        std::vector<char> h(size_);
+        for (const Sec& c : sec_) std::memcpy(h.data() + c.off, c.p, c.n);
+        buf.upload(h);
+        return;
+    }
+    for (const Sec& c : sec_) dev::h2d(buf.p + c.off, c.p, c.n);
+}
+
 void SlotMap::ref(const double* p, int8_t& slot, int64_t& off) const {
     // consecutive references usually fall in the same buffer; slots do not overlap
     if (base_[last_] && p >= base_[last_] && p < base_[last_] + cnt_[last_]) {
@@ -372,6 +384,12 @@ void GemmBatch::upload() {
         }
     part_.ensure(std::max<size_t>(psz, 1));
     red_.clear();
+    if (psz == 0 && live.size() == g_.size()) {
+        // nothing to split or drop: the lists are already laid out (groups
+        // in order, terms contiguous per group, tiles numbered in order)
+        upload_lists();
+        return;
+    }
     std::vector<dev::GemmGroup> gs;
     std::vector<dev::GemmTerm> ts;
     gs.reserve(live.size());
@@ -386,7 +404,7 @@ void GemmBatch::upload() {
             c.term0 = (int)ts.size();
             c.tile0 = tiles;
             tiles += tl;
-            for (int t = 0; t < g.nterms; ++t) ts.push_back(t_[g.term0 + t]);
+            ts.insert(ts.end(), t_.begin() + g.term0, t_.begin() + g.term0 + g.nterms);
             gs.push_back(c);
             continue;
         }
@@ -454,7 +472,7 @@ void GemmBatch::upload_lists() {
     Packer pk;
     const size_t og = pk.add(g_), ot = pk.add(t_), otg = pk.add(tg);
     red_.pack(pk);
-    buf_.upload(pk.bytes());
+    pk.upload(buf_);
     dg_ = reinterpret_cast<const dev::GemmGroup*>(buf_.p + og);
     dt_ = reinterpret_cast<const dev::GemmTerm*>(buf_.p + ot);
     dtg_ = reinterpret_cast<const int*>(buf_.p + otg);
@@ -535,7 +553,7 @@ void AxpyBatch::attach(const char* dev_base) {
 void AxpyBatch::upload() {
     Packer pk;
     pack(pk);
-    buf_.upload(pk.bytes());
+    pk.upload(buf_);
     attach(buf_.p);
 }
 void AxpyBatch::run(const dev::Bases& b) const {

@@ -43,12 +43,15 @@ class DevArr {
         if (p) dev::release(p);  // stream-ordered pool
     }
     void upload(const std::vector<T>& v) {
-        if (v.size() > cap) {
+        ensure(v.size());
+        if (!v.empty()) dev::h2d(p, v.data(), v.size() * sizeof(T));
+    }
+    void ensure(size_t n) {  // capacity for n elements (contents not kept)
+        if (n > cap) {
             if (p) dev::release(p);
-            cap = v.size() + v.size() / 2 + 16;
+            cap = n + n / 2 + 16;
             p = static_cast<T*>(dev::alloc(cap * sizeof(T)));
         }
-        if (!v.empty()) dev::h2d(p, v.data(), v.size() * sizeof(T));
     }
     T* p = nullptr;
     size_t cap = 0;
@@ -58,17 +61,29 @@ class DevArr {
 // work list reaches the device in one copy.
 class Packer {
   public:
+    // places v at the next 256-byte boundary; v must stay unchanged until upload()
     template <class T>
     size_t add(const std::vector<T>& v) {
-        const size_t off = (h_.size() + 255) & ~size_t(255);
-        h_.resize(off + v.size() * sizeof(T));
-        if (!v.empty()) std::memcpy(h_.data() + off, v.data(), v.size() * sizeof(T));
+        const size_t off = (size_ + 255) & ~size_t(255);
+        if (!v.empty()) sec_.push_back({off, v.data(), v.size() * sizeof(T)});
+        size_ = off + v.size() * sizeof(T);
         return off;
     }
-    const std::vector<char>& bytes() const { return h_; }
+    size_t size() const { return size_; }
+    // copies the sections into buf (grown to size() bytes): small lists as
+    // one host image in one copy, large ones section by section straight from
+    // their vectors (the runtime stages pageable memory itself, so an image
+    // would only add a pass over the bytes)
+    void upload(DevArr<char>& buf) const;
 
   private:
-    std::vector<char> h_;
+    struct Sec {
+        size_t off;
+        const void* p;
+        size_t n;
+    };
+    std::vector<Sec> sec_;
+    size_t size_ = 0;
 };
 
 struct Bond {
