@@ -236,6 +236,7 @@ TwoOp make_twoop(const MPO& m, int i) {
     std::vector<double> acc(16 * row, 0.0);
     std::vector<char> hit(16 * row, 0);
     std::vector<size_t> touched;
+    std::vector<size_t> by_sp[16];
     O.by_out.assign((size_t)O.nout * 16, {});
     for (int wo = 0; wo < O.nout; ++wo) {
         auto& list = by_out[wo];
@@ -263,14 +264,18 @@ TwoOp make_twoop(const MPO& m, int i) {
                     }
             }
         }
-        std::sort(touched.begin(), touched.end());
-        for (size_t k : touched) {
-            const int sp = (int)(k / row);
-            const int rest = (int)(k % row);
-            if (acc[k] != 0.0)
-                O.by_out[(size_t)wo * 16 + sp].push_back({rest / 16, (rest % 16) / 4, rest % 4, acc[k]});
-            acc[k] = 0.0;
-            hit[k] = 0;
+        // ascending k: by output local state sp (k / row), then within it
+        for (auto& bk : by_sp) bk.clear();
+        for (size_t k : touched) by_sp[k / row].push_back(k);
+        for (int sp = 0; sp < 16; ++sp) {
+            std::sort(by_sp[sp].begin(), by_sp[sp].end());
+            for (size_t k : by_sp[sp]) {
+                const int rest = (int)(k - (size_t)sp * row);
+                if (acc[k] != 0.0)
+                    O.by_out[(size_t)wo * 16 + sp].push_back({rest / 16, (rest % 16) / 4, rest % 4, acc[k]});
+                acc[k] = 0.0;
+                hit[k] = 0;
+            }
         }
     }
     return O;
